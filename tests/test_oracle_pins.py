@@ -1,0 +1,284 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+The oracle (``oracle/ht_oracle.c``) is the unblocked stage-two algorithm
+(Section 3.1).  None of these tests re-types its loops: they check invariants of
+the problem statement (Section 1: Q (H,T) Z^H = (A,B) with unitary Q, Z, H
+Hessenberg, T triangular), the accuracy claim of Section 4 (backward errors of
+the order of machine precision), the index ranges drawn in Figure 3, the flop
+count of Section 3.1 in closed form, LAPACK reference routines, and exact
+rational arithmetic on tiny pencils.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.linalg import lapack
+from scipy.optimize import linear_sum_assignment
+
+from oracle import oracle as O
+from paper_2301_07964_amd import inputs
+from tests import lapack_ref as LR
+
+EPS = np.finfo(np.float64).eps          # 2^-52, the epsilon used for the 100 n eps bounds
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fro(x):
+    return np.linalg.norm(x)
+
+
+def check_invariants(Hin, Tin, H, T, Q, Z, tol_factor=100.0):
+    n = H.shape[0]
+    bound = tol_factor * n * EPS
+    # P1: exact zeros below the first subdiagonal of H and the diagonal of T
+    assert np.all(np.tril(H, -2) == 0)
+    assert np.all(np.tril(T, -1) == 0)
+    # P2: orthogonality
+    I = np.eye(n)
+    assert fro(Q.conj().T @ Q - I) <= bound
+    assert fro(Z.conj().T @ Z - I) <= bound
+    # P3: backward errors
+    assert fro(Q @ H @ Z.conj().T - Hin) / fro(Hin) <= bound
+    assert fro(Q @ T @ Z.conj().T - Tin) / fro(Tin) <= bound
+
+
+@pytest.mark.parametrize("n,r,seed", [(256, 8, 0), (97, 7, 1), (64, 16, 2), (33, 32, 3), (150, 1, 4), (41, 40, 5)])
+def test_invariants_real(n, r, seed):
+    Hin, Tin = inputs.rht_pencil(n, r, seed)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r)
+    check_invariants(Hin, Tin, H, T, Q, Z)
+
+
+@pytest.mark.parametrize("n,r,seed", [(120, 5, 0), (64, 8, 1), (37, 4, 2)])
+def test_invariants_complex(n, r, seed):
+    Hin, Tin = inputs.rht_pencil_complex(n, r, seed)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r)
+    check_invariants(Hin, Tin, H, T, Q, Z)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_q_z_first_columns_fixed(cplx):
+    """P4: no transformation touches index 1 (i1 >= 2), so Q e1 = Z e1 = e1 bitwise."""
+    n, r = 80, 6
+    Hin, Tin = (inputs.rht_pencil_complex if cplx else inputs.rht_pencil)(n, r, 7)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r)
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    assert np.array_equal(Q[:, 0], e1) and np.array_equal(Q[0, :], e1)
+    assert np.array_equal(Z[:, 0], e1) and np.array_equal(Z[0, :], e1)
+    assert H[0, 0] == Hin[0, 0] and T[0, 0] == Tin[0, 0]
+
+
+@pytest.mark.parametrize("n,r,cplx", [(60, 4, False), (128, 8, False), (200, 16, False), (48, 5, True), (96, 8, True)])
+def test_canonical_form_matches_lapack_gghrd(n, r, cplx):
+    """P5: after normalising the unimodular freedom, stage two equals LAPACK xGGHRD."""
+    Hin, Tin = (inputs.rht_pencil_complex if cplx else inputs.rht_pencil)(n, r, 11)
+    ref = LR.gghrd(Hin, Tin)
+    if ref is None:
+        pytest.skip("xGGHRD not exported by the bundled LAPACK")
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r)
+    a = LR.canonical(H, T, Q, Z)
+    b = LR.canonical(*ref)
+    for x, y in zip(a, b):
+        assert fro(x - y) / max(fro(y), 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("n,seed", [(3, 0), (5, 1), (6, 2), (8, 3)])
+def test_eigenvalues_brute_force_tiny(n, seed):
+    """P6: generalized eigenvalues of the output match roots of det(A - lam B) in exact arithmetic."""
+    r = max(1, n - 3)
+    Hin, Tin = inputs.rht_pencil(n, r, seed)
+    poly = LR.charpoly_exact(Hin, Tin)             # lowest degree first, exact
+    roots = np.roots([float(c) for c in reversed(poly)])
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r)
+    ev = sla.eigvals(H, T)
+    C = np.abs(roots[:, None] - ev[None, :])
+    i, j = linear_sum_assignment(C)
+    assert np.all(C[i, j] <= 1e-8 * (1 + np.abs(roots[i])))
+
+
+def test_larfg_matches_lapack_real():
+    """P7: xLARFG convention (sign of beta, v(0)=1, tau)."""
+    rng = np.random.default_rng(0)
+    for m in [2, 3, 7, 32]:
+        for s in [1.0, -1.0]:
+            x = rng.standard_normal(m)
+            x[0] = s * abs(x[0])
+            beta, v, tau = O.larfg(x[0], x[1:])
+            a2, x2, t2 = lapack.dlarfg(m, x[0], x[1:].copy())
+            assert np.isclose(beta, a2, rtol=1e-14, atol=0)
+            assert np.isclose(tau, t2, rtol=1e-14, atol=0)
+            assert np.allclose(v[1:], x2, rtol=1e-13, atol=1e-15)
+            G = np.eye(m) - tau * np.outer(v, v)
+            assert np.allclose(G.T @ x, beta * np.eye(m)[0], atol=1e-13)
+
+
+def test_larfg_matches_lapack_complex():
+    rng = np.random.default_rng(1)
+    for m in [2, 5, 16]:
+        x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        beta, v, tau = O.larfg(x[0], x[1:])
+        a2, x2, t2 = lapack.zlarfg(m, x[0], x[1:].copy())
+        assert abs(beta - a2) <= 1e-14 * abs(a2) and abs(np.imag(beta)) == 0
+        assert abs(tau - t2) <= 1e-14 * abs(t2)
+        assert np.allclose(v[1:], x2, rtol=1e-13, atol=1e-15)
+        G = np.eye(m) - tau * np.outer(v, v.conj())
+        assert np.allclose(G.conj().T @ x, beta * np.eye(m)[0], atol=1e-13)
+
+
+def test_larfg_special_cases():
+    """tau = 0 when x(1:) = 0 (real alpha); sgn(+0) = sgn(-0) = +1 (our reading)."""
+    beta, v, tau = O.larfg(3.0, np.zeros(4))
+    assert tau == 0 and beta == 3.0
+    for a0 in [0.0, -0.0]:
+        beta, v, tau = O.larfg(a0, np.array([3.0, 4.0]))
+        assert beta == -5.0 and tau == 1.0
+    beta, v, tau = O.larfg(2.0 + 1.0j, np.zeros(2, dtype=complex))
+    assert tau != 0 and beta.imag == 0      # a complex alpha is still rotated to a real beta
+
+
+@pytest.mark.parametrize("m,cplx", [(2, False), (5, False), (16, False), (32, False), (4, True), (16, True)])
+def test_rq_direction(m, cplx):
+    """P7 (RQ): the oracle's direction equals LAPACK xGERQF + xORGRQ's first row, and
+    B y is a multiple of e1 (y spans the null space of rows 2..m)."""
+    rng = np.random.default_rng(m)
+    B = rng.standard_normal((m, m)) + 3 * np.eye(m)
+    if cplx:
+        B = B + 1j * rng.standard_normal((m, m))
+    y = O.rq_direction(B)
+    if cplx:
+        rq, tau, _, info = lapack.zgerqf(B)
+        Qt, _, info2 = lapack.zungrq(rq, tau)
+    else:
+        rq, tau, _, info = lapack.dgerqf(B)
+        Qt, _, info2 = lapack.dorgrq(rq, tau)
+    yr = np.conj(Qt[0, :])
+    p = np.flatnonzero(yr != 0)[0]
+    yr = yr * np.conj(yr[p]) / abs(yr[p])
+    assert np.allclose(y, yr, rtol=0, atol=1e-12)
+    assert abs(np.linalg.norm(y) - 1) < 1e-14
+    assert np.linalg.norm((B @ y)[1:]) <= 1e-13 * np.linalg.norm(B)
+    assert np.imag(y[0]) == 0 and np.real(y[0]) > 0
+
+
+def test_rq_direction_singular_block():
+    """A singular block (saddle-point pencils): y is the null vector of the block."""
+    rng = np.random.default_rng(5)
+    m = 8
+    B = rng.standard_normal((m, m))
+    B[:, 3] = B[:, :3] @ np.array([1.0, -2.0, 0.5])    # rank deficient
+    y = O.rq_direction(B)
+    # B y = R e1 * R11; here rows 2..m of B y vanish and y is unit
+    assert np.linalg.norm((B @ y)[1:]) <= 1e-12 * np.linalg.norm(B)
+
+
+def test_figure3_ranges():
+    """P8: the update regions and annihilated entries of the first sweep drawn in Figure 3."""
+    g = json.load(open(os.path.join(GOLDEN, "fig3_unblocked_n10_r3.json")))
+    n, r = g["n"], g["r"]
+    Hin, Tin = inputs.rht_pencil(n, r, 0)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, r, jmax=1)
+    touchedH = np.zeros((n, n), bool)
+    touchedT = np.zeros((n, n), bool)
+    for st in g["steps"]:
+        for key, mask in (("left_H", touchedH), ("right_H", touchedH), ("left_T", touchedT), ("right_T", touchedT)):
+            (r0, r1), (c0, c1) = st[key]["rows"], st[key]["cols"]
+            mask[r0 - 1:r1, c0 - 1:c1] = True
+    # entries outside every shaded region are bitwise unchanged
+    assert np.array_equal(H[~touchedH], Hin[~touchedH])
+    assert np.array_equal(T[~touchedT], Tin[~touchedT])
+    # annihilated entries of the last step that touches them stay exact zeros after the sweep
+    for st in g["steps"]:
+        for (i, c) in st["zeroed_H"]:
+            assert H[i - 1, c - 1] == 0.0
+        for (i, c) in st["zeroed_T"]:
+            assert T[i - 1, c - 1] == 0.0
+    # the figure's outline: column 1 ends at row 2, column 2 at row 5
+    for c, last in enumerate(g["last_nonzero_row_H_cols_1_2"]):
+        assert np.all(H[last:, c] == 0) and H[last - 1, c] != 0
+    # the shaded regions are really updated (generic data)
+    assert np.all(H[1:4, 1:] != Hin[1:4, 1:])
+    # left update of step k=0 starts at column jb = 1 in H and i1 = 2 in T: T(2:4, 1) untouched
+    assert np.array_equal(T[1:4, 0], Tin[1:4, 0])
+
+
+@pytest.mark.parametrize("n,r", [(64, 4), (256, 8), (512, 16), (1024, 32), (2048, 16)])
+def test_flop_count_closed_form(n, r):
+    """P9: counted flops = 8 n^3 + O(r n^2).
+
+    Closed form: for sweep j the left reflectors cover rows j+1..n in blocks; a
+    row at position x is updated over (n-x) columns of H, (n-x) of T and n of Q;
+    the right reflectors over ~x rows of H, ~x of T and n of Z.  With 4 flops per
+    entry and reflector, sweep j costs 16 n (n-j) + O(r n), in total 8 n^3.
+    (Section 3.1 states 10 n^3; see the design notes.)
+    """
+    f = O.stage2_flops(n, r)
+    assert abs(f / (8.0 * n ** 3) - 1.0) <= 3.0 * r / n + 4.0 / n
+    if n >= 512:
+        assert f / n ** 3 < 8.4
+
+
+def test_complex_on_real_input_equals_real():
+    """P10: the complex oracle on a real pencil reproduces the real oracle."""
+    n, r = 70, 6
+    Hin, Tin = inputs.rht_pencil(n, r, 9)
+    a = O.stage2(Hin, Tin, r)
+    b = O.stage2(Hin.astype(complex), Tin.astype(complex), r)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y.real) and np.all(y.imag == 0)
+    assert 4 * a[4] == b[4]
+
+
+def test_edge_cases():
+    # n <= 2: nothing to do apart from zeroing
+    for n in [0, 1, 2]:
+        Hin, Tin = inputs.rht_pencil(n, 1, 0)
+        H, T, Q, Z, _ = O.stage2(Hin, Tin, 3)
+        assert np.array_equal(H, np.triu(Hin, -1)) and np.array_equal(T, np.triu(Tin))
+    # r = 1: already Hessenberg-triangular -> identity transformations
+    Hin, Tin = inputs.rht_pencil(40, 1, 1)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, 1)
+    assert np.array_equal(H, Hin) and np.array_equal(T, Tin)
+    assert np.array_equal(Q, np.eye(40)) and np.array_equal(Z, np.eye(40))
+    # r >= n-1 is accepted and gives an HT result
+    Hin, Tin = inputs.rht_pencil(20, 19, 2)
+    H, T, Q, Z, _ = O.stage2(Hin, Tin, 30)
+    check_invariants(Hin, Tin, H, T, Q, Z)
+
+
+def test_entries_outside_pattern_not_read():
+    n, r = 50, 4
+    Hin, Tin = inputs.rht_pencil(n, r, 3)
+    a = O.stage2(Hin, Tin, r)
+    Hg, Tg = Hin.copy(), Tin.copy()
+    i, c = np.indices((n, n))
+    Hg[i > c + r] = 1e300
+    Tg[i > c] = np.nan
+    b = O.stage2(Hg, Tg, r)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+
+
+def test_accumulates_into_given_q_z():
+    """Q <- Q Q2, Z <- Z Z2 when Q and Z are given (LAPACK COMPQ='V' semantics)."""
+    n, r = 45, 5
+    Hin, Tin = inputs.rht_pencil(n, r, 4)
+    rng = np.random.default_rng(0)
+    Q0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Z0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    H1, T1, Q1, Z1, _ = O.stage2(Hin, Tin, r)
+    H2, T2, Q2, Z2, _ = O.stage2(Hin, Tin, r, Q=Q0, Z=Z0)
+    assert np.array_equal(H1, H2) and np.array_equal(T1, T2)
+    assert np.allclose(Q2, Q0 @ Q1, atol=1e-13) and np.allclose(Z2, Z0 @ Z1, atol=1e-13)
+
+
+def test_partial_sweeps_prefix():
+    """Running sweeps 1..s and then the rest is the same as one run (used for bounded CPU samples)."""
+    n, r = 60, 5
+    Hin, Tin = inputs.rht_pencil(n, r, 6)
+    full = O.stage2(Hin, Tin, r)
+    part = O.stage2(Hin, Tin, r, jmax=7)
+    assert part[4] < full[4]
+    assert np.all(np.tril(part[0][:, :7], -2) == 0)

@@ -1,0 +1,144 @@
+/*
+ * ht.h -- C ABI of libht, a Hessenberg-triangular reduction library for AMD
+ * MI355X (gfx950).
+ *
+ * Method: Steel & Vandebril, "Parallel two-stage reduction to
+ * Hessenberg-triangular form" (arXiv 2301.07964).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are square, n x n, column major: element (i,j) (0-based) lives at
+ *    p[i + j*ld].  Real matrices are double; complex matrices are interleaved
+ *    (re, im) pairs of double (C99 double _Complex / hipDoubleComplex layout).
+ *  - Matrix pointers are DEVICE pointers (memory from hipMalloc or any
+ *    allocator that returns device-accessible memory, e.g. torch).  The caller
+ *    owns them; the library never frees or retains them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call validates its arguments on the host, then only ENQUEUES work on
+ *    `stream` and returns; results are ready after the stream synchronises.
+ *    Calls on different streams may run concurrently; calls that share a
+ *    matrix must be ordered by the caller.
+ *  - Workspace is taken from a cache inside the library, one per (device,
+ *    stream); it grows on demand (hipMalloc, which synchronises the device)
+ *    and is reused afterwards.  ht_workspace_bytes() reports the size a call
+ *    needs, for admission control by a caller that budgets device memory.
+ *  - Return value: 0 = enqueued; -k = argument k is invalid (LAPACK INFO
+ *    style, 1-based); > 0 = HT_ERR_* (a HIP failure).  Asynchronous kernel
+ *    faults surface at the caller's synchronisation of `stream`.
+ *  - Thread safety: calls from several host threads are safe when they use
+ *    different streams.
+ */
+#ifndef HT_H
+#define HT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HT_OK 0
+#define HT_ERR_HIP 1     /* a HIP runtime call failed */
+#define HT_ERR_NOMEM 2   /* device workspace allocation failed */
+#define HT_ERR_LAUNCH 3  /* a kernel launch failed */
+#define HT_ERR_NOTSUP 4  /* configuration not supported by this build */
+
+/*
+ * ht_stage2 -- reduce an r-Hessenberg-triangular pencil to Hessenberg-
+ * triangular form (stage two; Section 3, unblocked algorithm in the appendix,
+ * blocked as generate + apply phases, Section 3.2).
+ *
+ *   H  (in/out) n x n: on entry r-Hessenberg (H[i,j] = 0 for i > j + r; the
+ *      entries below that band are NOT read); on exit upper Hessenberg with
+ *      exact zeros below the first subdiagonal.
+ *   T  (in/out) n x n: on entry upper triangular (entries below the diagonal
+ *      are NOT read); on exit upper triangular with exact zeros below.
+ *   Q, Z (in/out) n x n or NULL: on exit Q <- Q*Q2 and Z <- Z*Z2 where
+ *      (H_in, T_in) = Q2 (H_out, T_out) Z2^H (pass the identity to obtain Q2,
+ *      Z2; pass stage-one factors to obtain the whole reduction).  NULL means
+ *      "do not accumulate".
+ *   n >= 0, r >= 1 (r >= n-1 is accepted; r == 1 or n <= 2 only writes the
+ *      exact zeros), ld >= max(1, n) is shared by the four matrices.
+ * Errors: -5 n < 0, -6 r < 1, -7 ld < max(1,n), -1/-2 NULL H/T (n > 0).
+ * Reflector conventions: LAPACK xLARFG; left updates use G^H; the opposite
+ * reflector is generated from the first row of the RQ orthogonal factor of
+ * the current diagonal block of T, normalised to a real positive first
+ * nonzero entry.
+ */
+int ht_stage2(double *H, double *T, double *Q, double *Z,
+              int64_t n, int64_t r, int64_t ld, void *stream);
+
+/* Complex128 analogue of ht_stage2 (interleaved re/im doubles). */
+int ht_stage2_z(void *H, void *T, void *Q, void *Z,
+                int64_t n, int64_t r, int64_t ld, void *stream);
+
+/*
+ * ht_stage2_q -- ht_stage2 with an explicit number q of sweeps per delayed
+ * update group (Section 3.2).  q = 0 selects the built-in choice.  Requires
+ * 1 <= q <= r (else -8).  Used by the autotuner and by tests.
+ */
+int ht_stage2_q(double *H, double *T, double *Q, double *Z,
+                int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
+int ht_stage2_z_q(void *H, void *T, void *Q, void *Z,
+                  int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
+
+/*
+ * ht_stage2_batched -- `count` independent stage-two reductions in one
+ * persistent launch (pencils of uneven n and r).  H, T, Q, Z, n, r, ld, q are
+ * HOST arrays of length `count` (Q[b] / Z[b] may be NULL; q[b] = 0 selects the
+ * built-in choice; the q array itself may be NULL); they are copied before the
+ * call returns.  Each pencil's arithmetic is identical to a single
+ * ht_stage2_q call with the same (n, r, q).
+ * Errors: -1 count < 0, -2..-5 NULL array, -6 n array, -7 r array,
+ * -8 ld array (first offending entry decides), -9 q array.
+ */
+int ht_stage2_batched(int64_t count, double *const *H, double *const *T,
+                      double *const *Q, double *const *Z, const int64_t *n,
+                      const int64_t *r, const int64_t *ld, const int64_t *q,
+                      void *stream);
+int ht_stage2_batched_z(int64_t count, void *const *H, void *const *T,
+                        void *const *Q, void *const *Z, const int64_t *n,
+                        const int64_t *r, const int64_t *ld, const int64_t *q,
+                        void *stream);
+
+/*
+ * ht_rhess -- stage one: reduce a dense pencil (A, B) to r-Hessenberg-
+ * triangular form (Section 2.2, blocked stage-one algorithm in the appendix),
+ * after a Householder QR factorisation of B (Section 4).  Panel width n_b = r,
+ * p = 8 panel blocks per QR.
+ *   A, B (in/out): on exit A is r-Hessenberg (exact zeros below) and B upper
+ *   triangular (exact zeros below); Q <- Q*Q1, Z <- Z*Z1 with
+ *   (A_in, B_in) = Q1 (A_out, B_out) Z1^H; Q, Z may be NULL.
+ * Errors as ht_stage2.
+ */
+int ht_rhess(double *A, double *B, double *Q, double *Z,
+             int64_t n, int64_t r, int64_t ld, void *stream);
+int ht_rhess_z(void *A, void *B, void *Q, void *Z,
+               int64_t n, int64_t r, int64_t ld, void *stream);
+
+/*
+ * Device workspace (bytes) that a call with these sizes takes from the
+ * per-stream cache (is_complex: 0 real, 1 complex; q = 0: built-in choice).
+ * Returns -1 for invalid sizes.
+ */
+int64_t ht_workspace_bytes(int64_t n, int64_t r, int64_t q, int is_complex);
+
+/* Release the calling thread's cached workspaces on the current device. */
+void ht_release_workspace(void);
+
+/* The built-in group size q for (n, r). */
+int64_t ht_default_q(int64_t n, int64_t r);
+
+/* Static description of an error code (never NULL). */
+const char *ht_strerror(int code);
+
+/* Library version string. */
+const char *ht_version(void);
+
+/* Diagnostic text of the calling thread's last launch failure ("" if none). */
+const char *ht_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HT_H */

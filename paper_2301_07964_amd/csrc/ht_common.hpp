@@ -1,0 +1,86 @@
+// ht_common.hpp -- scalar helpers, index map and launch geometry shared by the
+// HIP kernels of libht (gfx950 only).
+//
+// Index notation follows the paper (Steel & Vandebril, Section 3 and the
+// stage-two algorithms of the appendix): sweeps j and matrix rows/columns are
+// 1-based in the index formulas, converted to 0-based only at memory access.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ht {
+
+// ------------------------------------------------------------------ scalars
+struct zd { double re, im; };
+
+__host__ __device__ inline double re(double a) { return a; }
+__host__ __device__ inline double re(zd a) { return a.re; }
+__host__ __device__ inline double im(double) { return 0.0; }
+__host__ __device__ inline double im(zd a) { return a.im; }
+template <class S> __host__ __device__ inline S mk(double r, double i);
+template <> __host__ __device__ inline double mk<double>(double r, double) { return r; }
+template <> __host__ __device__ inline zd mk<zd>(double r, double i) { zd z; z.re = r; z.im = i; return z; }
+template <class S> __host__ __device__ inline S zero() { return mk<S>(0.0, 0.0); }
+template <class S> __host__ __device__ inline S one() { return mk<S>(1.0, 0.0); }
+
+__host__ __device__ inline double conj_(double a) { return a; }
+__host__ __device__ inline zd conj_(zd a) { return mk<zd>(a.re, -a.im); }
+__host__ __device__ inline double add(double a, double b) { return a + b; }
+__host__ __device__ inline zd add(zd a, zd b) { return mk<zd>(a.re + b.re, a.im + b.im); }
+__host__ __device__ inline double sub(double a, double b) { return a - b; }
+__host__ __device__ inline zd sub(zd a, zd b) { return mk<zd>(a.re - b.re, a.im - b.im); }
+__host__ __device__ inline double mul(double a, double b) { return a * b; }
+__host__ __device__ inline zd mul(zd a, zd b) { return mk<zd>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+// conj(a) * b
+__host__ __device__ inline double cmul(double a, double b) { return a * b; }
+__host__ __device__ inline zd cmul(zd a, zd b) { return mk<zd>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re); }
+__host__ __device__ inline double scal(double a, double s) { return a * s; }
+__host__ __device__ inline zd scal(zd a, double s) { return mk<zd>(a.re * s, a.im * s); }
+__host__ __device__ inline double abs2(double a) { return a * a; }
+__host__ __device__ inline double abs2(zd a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline bool iszero(double a) { return a == 0.0; }
+__host__ __device__ inline bool iszero(zd a) { return a.re == 0.0 && a.im == 0.0; }
+// 1 / (c + i d), Smith's method
+__host__ __device__ inline double recip(double a) { return 1.0 / a; }
+__host__ __device__ inline zd recip(zd z) {
+    double c = z.re, d = z.im;
+    if (fabs(c) >= fabs(d)) { double e = d / c, f = c + d * e; return mk<zd>(1.0 / f, -e / f); }
+    double e = c / d, f = d + c * e; return mk<zd>(e / f, -1.0 / f);
+}
+
+// ------------------------------------------------------- wave reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline zd wave_sum(zd v) { return mk<zd>(wave_sum(v.re), wave_sum(v.im)); }
+// sum over aligned groups of G lanes (G power of two <= 64)
+template <int G> __device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int G> __device__ inline zd group_sum(zd v) { return mk<zd>(group_sum<G>(v.re), group_sum<G>(v.im)); }
+
+// ------------------------------------------------------- stage-two index map
+// 1-based formulas of the unblocked stage-two algorithm.
+__host__ __device__ inline int64_t nblocks(int64_t n, int64_t r, int64_t j) {  // blocks with >= 2 rows
+    return n - j - 2 < 0 ? 0 : 1 + (n - j - 2) / r;
+}
+__host__ __device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
+__host__ __device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// Band storage of a scratch copy: element (i,c) (0-based) with
+// -BU <= i - c <= BL lives at B[(i - c + BU) + c * ldb], ldb = BU + BL + 1.
+struct Band {
+    int64_t BU, BL, ldb;
+    __host__ __device__ inline int64_t idx(int64_t i0, int64_t c0) const { return (i0 - c0 + BU) + c0 * ldb; }
+};
+
+// Maximum supported r on the GPU path: a lazy update column segment
+// (q + r - 1 <= 63 rows) must fit one 64-lane wavefront.
+constexpr int kMaxR = 32;
+constexpr int kWin = 64;     // padded window-factor order (>= q + r - 1)
+
+}  // namespace ht

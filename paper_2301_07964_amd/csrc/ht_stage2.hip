@@ -1,0 +1,241 @@
+// ht_stage2.hip -- stage two of the two-stage Hessenberg-triangular reduction
+// (Steel & Vandebril, Section 3) on gfx950, and the C ABI declared in ht.h.
+//
+// Per group of q sweeps (Section 3.2):
+//   1. copy the diagonal band of H and T that the generate phase touches into
+//      a scratch band (the delayed updates later recompute every entry of H
+//      and T from the pre-group values, so generation works on a copy);
+//   2. generate phase (ht_generate.hpp): reflectors of the q sweeps;
+//   3. application phase (ht_update.hpp): right updates of H, T, Z and Q,
+//      then left updates of H and T.
+// All work is enqueued on the caller's stream.
+#include "ht_common.hpp"
+#include "ht_generate.hpp"
+#include "ht_update.hpp"
+#include "ht_workspace.hpp"
+#include "ht.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+namespace ht {
+
+// ------------------------------------------------------- error reporting
+thread_local char g_errmsg[256] = "";
+
+int launch_check(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return 0;
+    snprintf(g_errmsg, sizeof(g_errmsg), "%s: %s", what, hipGetErrorString(e));
+    return HT_ERR_LAUNCH;
+}
+
+// --------------------------------------------------------------- helpers
+template <class S>
+__global__ __launch_bounds__(256) void k_band_copy(const S *__restrict__ H, const S *__restrict__ T, int64_t ld,
+                                                   S *SH, S *ST, Band B, int64_t n, int64_t c0,
+                                                   int *progress, int nprog)
+{
+    if (blockIdx.x == 0 && (int)threadIdx.x < nprog) progress[threadIdx.x] = 0;
+    const int64_t c = c0 + blockIdx.x;
+    if (c >= n) return;
+    const int64_t ilo = i64max(0, c - B.BU), ihi = i64min(n - 1, c + B.BL);
+    for (int64_t i = ilo + threadIdx.x; i <= ihi; i += blockDim.x) {
+        SH[B.idx(i, c)] = H[i + c * ld];
+        ST[B.idx(i, c)] = T[i + c * ld];
+    }
+}
+
+// X(i, c) = 0 for i > c + off  (the exact zeros of the output contract, and the
+// "not read" entries of the input contract)
+template <class S>
+__global__ __launch_bounds__(256) void k_zero_lower(S *X, int64_t ld, int64_t n, int64_t off)
+{
+    const int64_t c = blockIdx.x;
+    for (int64_t i = c + off + 1 + threadIdx.x; i < n; i += blockDim.x) X[i + c * ld] = zero<S>();
+}
+
+template <class S>
+static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st)
+{
+    if (n <= 0 || !X) return 0;
+    hipLaunchKernelGGL(k_zero_lower<S>, dim3((unsigned)n), dim3(256), 0, st, X, ld, n, off);
+    return launch_check("k_zero_lower");
+}
+
+inline int64_t default_q(int64_t n, int64_t r) { (void)n; return r; }
+
+struct Geometry {
+    int64_t n, r, q, kext, BU, BL, ldb;
+    size_t esz;
+    size_t off_SH, off_ST, off_VL, off_VR, off_TL, off_TR, off_prog, total;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
+{
+    Geometry g{};
+    g.n = n; g.r = r; g.q = q; g.esz = esz;
+    g.kext = nblocks(n, r, 1) + 1;
+    g.BU = (q + 1) * r;
+    g.BL = 2 * r;
+    g.ldb = g.BU + g.BL + 1;
+    size_t o = 0;
+    g.off_SH = o; o += al((size_t)n * g.ldb * esz);
+    g.off_ST = o; o += al((size_t)n * g.ldb * esz);
+    g.off_VL = o; o += al((size_t)q * g.kext * r * esz);
+    g.off_VR = o; o += al((size_t)q * g.kext * r * esz);
+    g.off_TL = o; o += al((size_t)q * g.kext * esz);
+    g.off_TR = o; o += al((size_t)q * g.kext * esz);
+    g.off_prog = o; o += al((size_t)q * sizeof(int));
+    g.total = o;
+    return g;
+}
+
+template <class S>
+static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, int64_t q, void *stream)
+{
+    if (n < 0) return -5;
+    if (r < 1) return -6;
+    if (ld < (n > 1 ? n : 1)) return -7;
+    if (n > 0 && !H) return -1;
+    if (n > 0 && !T) return -2;
+    if (n == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    (void)hipGetLastError();           // clear a stale error left by earlier HIP calls
+    g_errmsg[0] = 0;
+    // entries outside the r-HT pattern are not read: they are overwritten by 0
+    if ((rc = zero_lower(H, ld, n, r, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
+    const int64_t re_ = i64min(r, i64max(n - 1, 1));
+    if (n <= 2 || re_ <= 1) {
+        if ((rc = zero_lower(H, ld, n, 1, st))) return rc;
+        return 0;
+    }
+    if (re_ > kMaxR) return HT_ERR_NOTSUP;
+    if (q == 0) q = default_q(n, re_);
+    if (q < 1 || q > re_) return -8;
+    const Geometry g = geometry(n, re_, q, sizeof(S));
+    unsigned char *ws = (unsigned char *)workspace_get(g.total, st, &rc);
+    if (!ws) return rc;
+    S *SH = (S *)(ws + g.off_SH), *ST = (S *)(ws + g.off_ST);
+    S *VL = (S *)(ws + g.off_VL), *VR = (S *)(ws + g.off_VR);
+    S *TL = (S *)(ws + g.off_TL), *TR = (S *)(ws + g.off_TR);
+    int *prog = (int *)(ws + g.off_prog);
+    const Band B{g.BU, g.BL, g.ldb};
+    const int64_t rr = re_;
+    const size_t lds_right = (size_t)(2 * rr) * 64 * sizeof(S);
+    const size_t lds_left = lds_right + (size_t)64 * 65 * sizeof(S);
+
+    for (int64_t j1 = 1; j1 <= n - 2; j1 += q) {
+        const int64_t j2 = i64min(j1 + q - 1, n - 2);
+        const int64_t qg = j2 - j1 + 1;
+        const int64_t kmax = nblocks(n, rr, j1);
+        const int64_t kext = kmax + 1;
+        // 1. scratch band
+        hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
+                           (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)qg);
+        if ((rc = launch_check("k_band_copy"))) return rc;
+        // 2. generate
+        GenArgs<S> ga;
+        ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
+        ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
+        hipLaunchKernelGGL(k_generate<S>, dim3((unsigned)qg), dim3(256), 0, st, ga);
+        if ((rc = launch_check("k_generate"))) return rc;
+        // 3. application: right updates
+        UpdArgs<S> ua;
+        ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;
+        ua.VL = VL; ua.TL = TL; ua.VR = VR; ua.TR = TR;
+        const int64_t np = (n + 63) / 64;
+        int nj = 0;
+        int64_t tot = 0;
+        auto addjob = [&](S *X, int side, int64_t lim) {
+            if (!X) return;
+            ua.job[nj].X = X; ua.job[nj].ld = ld; ua.job[nj].lim = lim; ua.job[nj].npanels = np; ua.job[nj].side = side;
+            ++nj; tot += np;
+        };
+        addjob(H, 1, (q + 2) * rr);
+        addjob(T, 1, (q + 1) * rr);
+        addjob(Z, 1, -1);
+        addjob(Q, 0, -1);
+        ua.njobs = nj;
+        hipLaunchKernelGGL(k_update_right<S>, dim3((unsigned)tot), dim3(64), lds_right, st, ua);
+        if ((rc = launch_check("k_update_right"))) return rc;
+        // left updates of H and T
+        nj = 0; tot = 0;
+        addjob(H, 0, (q + 1) * rr);
+        addjob(T, 0, (q + 1) * rr);
+        ua.njobs = nj;
+        hipLaunchKernelGGL(k_update_left<S>, dim3((unsigned)tot), dim3(64), lds_left, st, ua);
+        if ((rc = launch_check("k_update_left"))) return rc;
+    }
+    if ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
+    return 0;
+}
+
+}  // namespace ht
+
+// =================================================================== C ABI
+extern "C" {
+
+int ht_stage2(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, void *stream)
+{
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, 0, stream);
+}
+
+int ht_stage2_q(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, int64_t q,
+                void *stream)
+{
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, q, stream);
+}
+
+int ht_stage2_z(void *H, void *T, void *Q, void *Z, int64_t n, int64_t r, int64_t ld, void *stream)
+{
+    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, 0, stream);
+}
+
+int ht_stage2_z_q(void *H, void *T, void *Q, void *Z, int64_t n, int64_t r, int64_t ld, int64_t q, void *stream)
+{
+    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, q, stream);
+}
+
+int64_t ht_workspace_bytes(int64_t n, int64_t r, int64_t q, int is_complex)
+{
+    if (n < 0 || r < 1 || q < 0) return -1;
+    if (n <= 2) return 0;
+    const int64_t re_ = ht::i64min(r, n - 1);
+    if (re_ <= 1) return 0;
+    if (q == 0) q = ht::default_q(n, re_);
+    if (q > re_) return -1;
+    return (int64_t)ht::geometry(n, re_, q, is_complex ? 16 : 8).total;
+}
+
+int64_t ht_default_q(int64_t n, int64_t r)
+{
+    if (n <= 2 || r <= 1) return 1;
+    return ht::default_q(n, ht::i64min(r, n - 1));
+}
+
+const char *ht_strerror(int code)
+{
+    if (code == 0) return "success";
+    if (code < 0) return "invalid argument";
+    switch (code) {
+    case HT_ERR_HIP: return "HIP runtime error";
+    case HT_ERR_NOMEM: return "device workspace allocation failed";
+    case HT_ERR_LAUNCH: return "kernel launch failed";
+    case HT_ERR_NOTSUP: return "configuration not supported (r > 32 on the GPU path)";
+    default: return "unknown error";
+    }
+}
+
+const char *ht_version(void) { return "libht 0.1 (gfx950)"; }
+
+const char *ht_last_error_message(void) { return ht::g_errmsg; }
+
+}  // extern "C"
+
+extern "C" void ht_release_workspace(void) { ht::workspace_release_all_current_device(); }

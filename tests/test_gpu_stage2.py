@@ -1,0 +1,110 @@
+"""GPU parity of ht_stage2 / ht_stage2_z (C ABI through the Python binding)
+against the CPU oracle (unblocked stage two, Section 3.1), plus the invariants
+of the output contract.  Tolerance: 1e-9 relative Frobenius norm on each of
+H, T, Q and Z (delaying the updates reorders the arithmetic, not the
+reflectors)."""
+import numpy as np
+import pytest
+
+from paper_2301_07964_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+TOL = 1e-9
+
+
+def _ht():
+    import paper_2301_07964_amd as ht
+    return ht
+
+
+def run_gpu(H, T, r, q=0, accumulate=True):
+    ht = _ht()
+    n = H.shape[0]
+    Hd, Td = ht.colmajor(H), ht.colmajor(T)
+    Qd = Zd = None
+    if accumulate:
+        Qd = ht.colmajor(np.eye(n, dtype=H.dtype))
+        Zd = ht.colmajor(np.eye(n, dtype=H.dtype))
+    ht.stage2(Hd, Td, r, Qd, Zd, q=q)
+    torch.cuda.synchronize()
+    out = [ht.to_numpy(Hd), ht.to_numpy(Td)]
+    out += [ht.to_numpy(Qd), ht.to_numpy(Zd)] if accumulate else [None, None]
+    return out
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def check_parity(H, T, r, q=0):
+    from oracle import oracle as O
+    print(f"[parity] n={H.shape[0]} r={r} q={q} complex={np.iscomplexobj(H)}", flush=True)
+    ref = O.stage2(H, T, r)
+    got = run_gpu(H, T, r, q)
+    errs = [rel(g, o) for g, o in zip(got, ref[:4])]
+    assert max(errs) <= TOL, f"relative errors H,T,Q,Z = {errs}"
+    n = H.shape[0]
+    # exact zero structure and the first columns of Q, Z
+    assert np.all(np.tril(got[0], -2) == 0) and np.all(np.tril(got[1], -1) == 0)
+    if n > 0:
+        e1 = np.zeros(n)
+        e1[0] = 1
+        assert np.array_equal(got[2][:, 0], e1) and np.array_equal(got[3][:, 0], e1)
+    return errs
+
+
+@pytest.mark.parametrize("n,r,seed", [(256, 8, 0), (300, 7, 1), (200, 16, 2), (130, 32, 3), (97, 4, 4), (64, 3, 5)])
+def test_parity_real(n, r, seed):
+    H, T = inputs.rht_pencil(n, r, seed)
+    check_parity(H, T, r)
+
+
+@pytest.mark.parametrize("q", [1, 2, 5, 8])
+def test_parity_group_sizes(q):
+    H, T = inputs.rht_pencil(181, 8, 10)
+    check_parity(H, T, 8, q)
+
+
+@pytest.mark.parametrize("n,r,seed", [(150, 5, 0), (128, 8, 1), (70, 16, 2)])
+def test_parity_complex(n, r, seed):
+    H, T = inputs.rht_pencil_complex(n, r, seed)
+    check_parity(H, T, r)
+
+
+@pytest.mark.parametrize("n,r", [(0, 3), (1, 3), (2, 3), (3, 1), (3, 2), (5, 4), (12, 30), (40, 1)])
+def test_edge_sizes(n, r):
+    H, T = inputs.rht_pencil(n, min(r, max(n - 1, 0)), 3)
+    check_parity(H, T, r)
+
+
+def test_no_accumulation_matches():
+    H, T = inputs.rht_pencil(160, 8, 7)
+    a = run_gpu(H, T, 8)
+    b = run_gpu(H, T, 8, accumulate=False)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_deterministic():
+    H, T = inputs.rht_pencil(333, 16, 8)
+    a = run_gpu(H, T, 16)
+    b = run_gpu(H, T, 16)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_invalid_arguments():
+    ht = _ht()
+    n = 8
+    H = ht.colmajor(np.eye(n))
+    with pytest.raises(ht.HTError) as e:
+        ht.stage2(H, H.clone(), 0)
+    assert e.value.code == -6
+    import ctypes
+    assert ht.lib().ht_stage2(None, None, None, None, -1, 2, 1, None) == -5
+    assert ht.lib().ht_stage2(None, None, None, None, 4, 2, 2, None) == -7
+    assert ht.lib().ht_stage2(None, None, None, None, 4, 2, 4, None) == -1
+    assert ht.lib().ht_stage2_q(ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(H.data_ptr()), None, None, 8, 2, 8, 3, None) == -8

@@ -1,0 +1,61 @@
+"""The C-ABI library loads on the CPU host and exports every function that
+include/ht.h declares (no compute call: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2301_07964_amd", "libht.so")
+HDR = os.path.join(ROOT, "include", "ht.h")
+
+
+def declared_functions():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ht_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("ht_stage2", "ht_stage2_z", "ht_rhess", "ht_rhess_z", "ht_stage2_batched",
+                 "ht_stage2_batched_z", "ht_workspace_bytes", "ht_strerror"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")
+def test_host_only_entry_points():
+    L = ctypes.CDLL(LIB)
+    L.ht_strerror.restype = ctypes.c_char_p
+    L.ht_workspace_bytes.restype = ctypes.c_int64
+    L.ht_workspace_bytes.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_int]
+    L.ht_default_q.restype = ctypes.c_int64
+    L.ht_default_q.argtypes = [ctypes.c_int64] * 2
+    assert L.ht_strerror(0) == b"success"
+    assert L.ht_strerror(-3) == b"invalid argument"
+    assert L.ht_workspace_bytes(-1, 4, 0, 0) == -1
+    assert L.ht_workspace_bytes(2, 4, 0, 0) == 0
+    assert L.ht_workspace_bytes(100, 8, 0, 1) > L.ht_workspace_bytes(100, 8, 0, 0) > 0
+    assert L.ht_workspace_bytes(100, 8, 9, 0) == -1          # q > r
+    assert 1 <= L.ht_default_q(16384, 32) <= 32
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")
+def test_argument_errors_need_no_device():
+    """Argument validation happens on the host before any HIP call."""
+    L = ctypes.CDLL(LIB)
+    f = L.ht_stage2
+    f.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] * 3 + [ctypes.c_void_p]
+    assert f(None, None, None, None, -1, 2, 1, None) == -5
+    assert f(None, None, None, None, 4, 0, 4, None) == -6
+    assert f(None, None, None, None, 4, 2, 3, None) == -7
+    assert f(None, None, None, None, 4, 2, 4, None) == -1
+    assert f(None, None, None, None, 0, 2, 1, None) == 0

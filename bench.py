@@ -1,0 +1,200 @@
+#!/usr/bin/env python
+"""Stage-two Hessenberg-triangular reduction throughput on one MI355X.
+
+Default workload: one real FP64 r-Hessenberg-triangular pencil, n = 16384,
+r = 32, seed 0, Q and Z accumulated (the configuration the headline metric is
+quoted on).  A step is one full stage-two reduction ``ht_stage2`` of one
+pencil.  All inputs of the timed steps are resident in HBM before the timed
+region starts (one fresh copy per step, prepared beforehand); the timed region
+covers exactly ``--steps`` reductions bracketed by device synchronisation.
+
+Prints ONE JSON line: the metric (counted-flop GFLOP/s, see below), the
+roofline record of the dominant kernel (measured live with HIP events on the
+stream the kernels run on) and the CPU oracle timed on a bounded sample of the
+same workload on the host cores.
+
+Counted flops: 4 x reflector length x vectors updated for every reflector
+application of the unblocked algorithm (the paper's Section 3.1 states 10 n^3;
+the exact count of its algorithm is 8.0 n^3 + O(r n^2), 3.525e13 here).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def counted_flops_by_class(n, r):
+    """Algorithmic flops of the unblocked algorithm, split by where the blocked
+    implementation performs them: right-type applications (H, T, Z by the
+    right reflectors; Q by the left ones) and left-type (rows of H and T)."""
+    import numpy as np
+    right = left = 0.0
+    for j in range(1, n - 1):
+        nb = 1 + (n - j - 2) // r
+        k = np.arange(nb, dtype=np.int64)
+        jb = j + np.maximum(0, (k - 1) * r + 1)
+        i1 = j + k * r + 1
+        i2 = np.minimum(j + (k + 1) * r, n)
+        i3 = np.minimum(j + (k + 2) * r, n)
+        m = (i2 - i1 + 1).astype(np.float64)
+        right += float(np.sum(4.0 * m * (i3 + i2 + 2.0 * n)))
+        left += float(np.sum(4.0 * m * ((n - jb) + (n - i1 + 1))))
+    return right, left
+
+
+def cpu_baseline(H, T, r, target_s=15.0):
+    """The oracle on the host: the first s sweeps of the same pencil."""
+    import numpy as np
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    _, _, _, _, f1 = O.stage2(H, T, r, jmax=1)
+    t1 = time.perf_counter() - t0
+    s = max(1, min(H.shape[0] - 2, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    _, _, _, _, fs = O.stage2(H, T, r, jmax=s)
+    ts = time.perf_counter() - t0
+    return {"value": round(fs / ts / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {s} of {H.shape[0] - 2} sweeps of the same pencil (counted flops {fs:.3e}, {ts:.1f} s, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--r", type=int, default=32)
+    ap.add_argument("--q", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the reduction of one pencil is not sharded across devices).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2301_07964_amd as ht
+    from paper_2301_07964_amd import inputs
+
+    n, r = args.n, args.r
+    K, W = args.steps, args.warmup
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] generating r-HT pencil n={n} r={r} seed={args.seed}", file=sys.stderr, flush=True)
+    H, T = inputs.rht_pencil(n, r, args.seed)
+    Hd0, Td0 = ht.colmajor(H, dev), ht.colmajor(T, dev)
+    q = args.q if args.q else ht.default_q(n, r)
+    copies = []
+    for _ in range(W + K):
+        Hd = Hd0.clone(memory_format=torch.preserve_format)
+        Td = Td0.clone(memory_format=torch.preserve_format)
+        Qd = torch.eye(n, dtype=torch.float64, device=dev).t()
+        Zd = torch.eye(n, dtype=torch.float64, device=dev).t()
+        copies.append((Hd, Td, Qd, Zd))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    for i in range(W):
+        print(f"[bench] warmup {i + 1}/{W}", file=sys.stderr, flush=True)
+        Hd, Td, Qd, Zd = copies[i]
+        ht.stage2(Hd, Td, r, Qd, Zd, q=q, stream=stream)
+        torch.cuda.synchronize()
+
+    ht.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        Hd, Td, Qd, Zd = copies[W + i]
+        ht.stage2(Hd, Td, r, Qd, Zd, q=q, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ht.profile_enable(False)
+    prof = ht.profile_read()
+    print(f"[bench] {K} steps in {elapsed:.3f} s; kernel ms: "
+          + ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items()), file=sys.stderr, flush=True)
+
+    from oracle import oracle as O
+    total_flops = O.stage2_flops(n, r)
+    value = total_flops * K / elapsed / 1e9
+
+    # roofline of the dominant kernel class (algorithmic flops per launch / mean launch time)
+    fr, fl = counted_flops_by_class(n, r)
+    per_class_flops = {"update_right": fr, "update_left": fl}
+    dom = max(("update_right", "update_left", "generate"), key=lambda c: prof[c][0])
+    ms_tot, launches = prof[dom]
+    if dom in per_class_flops and launches > 0:
+        per_launch = per_class_flops[dom] * K / launches
+        achieved = per_launch / (ms_tot / launches * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": f"k_update_{dom.split('_')[1]}<double>",
+                    "algorithmic_flops_per_launch": per_launch,
+                    "mean_launch_ms": round(ms_tot / launches, 4)}
+    else:
+        roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": "k_generate<double>",
+                    "mean_launch_ms": round(ms_tot / max(launches, 1), 4)}
+
+    check = None
+    if not args.no_check:
+        Hd, Td, Qd, Zd = copies[-1]
+        eps = float(np.finfo(np.float64).eps)
+        Hr = torch.tril(Hd, -2).abs().max().item() if n > 2 else 0.0
+        Tr = torch.tril(Td, -1).abs().max().item() if n > 1 else 0.0
+        I = torch.eye(n, dtype=torch.float64, device=dev)
+        orth_q = torch.linalg.norm(Qd.t() @ Qd - I).item()
+        orth_z = torch.linalg.norm(Zd.t() @ Zd - I).item()
+        bH = (torch.linalg.norm(Qd @ Hd @ Zd.t() - Hd0) / torch.linalg.norm(Hd0)).item()
+        bT = (torch.linalg.norm(Qd @ Td @ Zd.t() - Td0) / torch.linalg.norm(Td0)).item()
+        bound = 100 * n * eps
+        check = {"exact_zeros": Hr == 0.0 and Tr == 0.0, "orth_Q": orth_q, "orth_Z": orth_z,
+                 "backward_H": bH, "backward_T": bT, "bound_100neps": bound,
+                 "ok": Hr == 0.0 and Tr == 0.0 and max(orth_q, orth_z, bH, bT) <= bound}
+        del I
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(H, T, r, args.cpu_seconds)
+
+    out = {
+        "metric": "stage-2 HT FP64 GFLOP/s + % FP64 peak at n=16384; batched pencils/s, p99 latency",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed / K * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"stage-2 reduction of one r-HT pencil, n={n}, r={r}, Q and Z accumulated, seed {args.seed}",
+                   "n": n, "r": r, "q": q, "seed": args.seed},
+        "pct_fp64_peak": round(value / (FP64_PEAK_TFLOPS * 1e3) * 100, 3),
+        "counted_flops_per_step": total_flops,
+        "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
+        "kernel_launches": {k: v[1] for k, v in prof.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "check": check,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,18 @@ const char *ht_version(void);
 /* Diagnostic text of the calling thread's last launch failure ("" if none). */
 const char *ht_last_error_message(void);
 
+/*
+ * Kernel timing (diagnostics).  ht_profile_enable(1) makes every later call
+ * bracket each kernel launch with HIP events recorded on its stream (small
+ * overhead).  ht_profile_read() waits for the recorded events, writes the
+ * summed milliseconds and the launch counts of each kernel class into
+ * ms[0..nclasses-1] / count[0..nclasses-1] (either may be NULL) and forgets
+ * the records.  Classes: 0 band copy, 1 generate, 2 right update, 3 left
+ * update, 4 exact-zero passes.  Returns 0 or HT_ERR_HIP.
+ */
+int ht_profile_enable(int on);
+int ht_profile_read(double *ms, int64_t *count, int nclasses);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,8 @@ def lib(with_torch: bool = True):
     L.ht_version.restype = ctypes.c_char_p
     L.ht_last_error_message.restype = ctypes.c_char_p
     L.ht_release_workspace.restype = None
+    L.ht_profile_enable.argtypes = [_int]
+    L.ht_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), _PI, _int]
     _lib = L
     return L
 
@@ -67,7 +69,24 @@ EXPORTS = (
     "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_batched",
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_workspace_bytes",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
+    "ht_profile_enable", "ht_profile_read",
 )
+
+PROFILE_CLASSES = ("band_copy", "generate", "update_right", "update_left", "zeroing")
+
+
+def profile_enable(on: bool = True):
+    """Bracket every following kernel launch with HIP events (diagnostics)."""
+    lib().ht_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """{class: (total_ms, launches)} of the launches recorded since the last read."""
+    k = len(PROFILE_CLASSES)
+    ms = (ctypes.c_double * k)()
+    cnt = (_i64 * k)()
+    _check(lib().ht_profile_read(ms, cnt, k), "ht_profile_read")
+    return {c: (ms[i], int(cnt[i])) for i, c in enumerate(PROFILE_CLASSES)}
 
 
 class HTError(RuntimeError):

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <mutex>
+#include <vector>
 
 namespace ht {
 
@@ -31,6 +33,36 @@ int launch_check(const char *what)
     snprintf(g_errmsg, sizeof(g_errmsg), "%s: %s", what, hipGetErrorString(e));
     return HT_ERR_LAUNCH;
 }
+
+// ------------------------------------------------------------ profiling
+// When enabled, every kernel launch of stage two is bracketed by HIP events
+// recorded on the caller's stream; ht_profile_read() sums the elapsed times
+// per kernel class.  Classes: 0 band copy, 1 generate, 2 right update,
+// 3 left update, 4 zeroing.
+constexpr int kProfClasses = 5;
+struct ProfRec { int cls; hipEvent_t a, b; };
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+    bool on = false;
+    int cls = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        on = hipEventRecord(a, st) == hipSuccess;
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back({cls, a, b});
+    }
+};
 
 // --------------------------------------------------------------- helpers
 template <class S>
@@ -57,10 +89,55 @@ __global__ __launch_bounds__(256) void k_zero_lower(S *X, int64_t ld, int64_t n,
     for (int64_t i = c + off + 1 + threadIdx.x; i < n; i += blockDim.x) X[i + c * ld] = zero<S>();
 }
 
+// Exact zeros of the structure after the last sweep j2 of a group.  In exact
+// arithmetic the delayed updates leave zeros there; in floating point they
+// leave rounding residue that the unblocked algorithm never has (it writes the
+// annihilated entries as zeros and never touches the others).  If the residue
+// stayed, the next group's scratch copy would inherit it and the generate
+// phase's restricted update ranges would treat it inconsistently, and the
+// mismatch feeds back from group to group.  Below the diagonal, T keeps only
+// the blocks I(j2,k) x I(j2,k) without their first column; H keeps the first
+// subdiagonal for columns <= j2, and for later columns the r-band plus the
+// fill blocks I(j2,k+1) x (I(j2,k) minus its first column).
+template <class S>
+__global__ __launch_bounds__(256) void k_clean(S *H, S *T, int64_t ld, int64_t n, int64_t r, int64_t j2,
+                                               int64_t c0, int64_t depth)
+{
+    const int64_t c = c0 + blockIdx.x;              // 0-based column
+    if (c >= n) return;
+    const int64_t c1 = c + 1;                       // 1-based column
+    const int64_t nb2 = nblocks(n, r, j2);
+    // block of sweep j2 that contains column c1 (if any)
+    int64_t kb = -1, a = 0, b = 0;
+    if (c1 >= j2 + 1) {
+        kb = (c1 - j2 - 1) / r;
+        if (kb >= nb2) kb = -1;
+        else { a = j2 + kb * r + 1; b = i64min(a + r - 1, n); }
+    }
+    const int64_t rend = i64min(n, c1 + depth);      // 1-based last row examined
+    for (int64_t i1b = c1 + 1 + threadIdx.x; i1b <= rend; i1b += blockDim.x) {
+        // T
+        bool keepT = (kb >= 0 && c1 > a && i1b <= b);
+        if (!keepT) T[(i1b - 1) + c * ld] = zero<S>();
+        // H
+        bool keepH;
+        if (c1 <= j2) keepH = (i1b <= c1 + 1);
+        else {
+            keepH = (i1b <= c1 + r);
+            if (!keepH && kb >= 0 && c1 > a) {
+                const int64_t a2 = a + r, b2 = i64min(a2 + r - 1, n);
+                keepH = (a2 <= n && i1b >= a2 && i1b <= b2);
+            }
+        }
+        if (!keepH) H[(i1b - 1) + c * ld] = zero<S>();
+    }
+}
+
 template <class S>
 static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st)
 {
     if (n <= 0 || !X) return 0;
+    ProfScope ps(4, st);
     hipLaunchKernelGGL(k_zero_lower<S>, dim3((unsigned)n), dim3(256), 0, st, X, ld, n, off);
     return launch_check("k_zero_lower");
 }
@@ -136,15 +213,17 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         const int64_t kmax = nblocks(n, rr, j1);
         const int64_t kext = kmax + 1;
         // 1. scratch band
+        { ProfScope ps(0, st);
         hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
                            (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)qg);
-        if ((rc = launch_check("k_band_copy"))) return rc;
+        if ((rc = launch_check("k_band_copy"))) return rc; }
         // 2. generate
         GenArgs<S> ga;
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
         ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
+        { ProfScope ps(1, st);
         hipLaunchKernelGGL(k_generate<S>, dim3((unsigned)qg), dim3(256), 0, st, ga);
-        if ((rc = launch_check("k_generate"))) return rc;
+        if ((rc = launch_check("k_generate"))) return rc; }
         // 3. application: right updates
         UpdArgs<S> ua;
         ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;
@@ -162,15 +241,23 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         addjob(Z, 1, -1);
         addjob(Q, 0, -1);
         ua.njobs = nj;
+        { ProfScope ps(2, st);
         hipLaunchKernelGGL(k_update_right<S>, dim3((unsigned)tot), dim3(64), lds_right, st, ua);
-        if ((rc = launch_check("k_update_right"))) return rc;
+        if ((rc = launch_check("k_update_right"))) return rc; }
         // left updates of H and T
         nj = 0; tot = 0;
         addjob(H, 0, (q + 1) * rr);
         addjob(T, 0, (q + 1) * rr);
         ua.njobs = nj;
+        { ProfScope ps(3, st);
         hipLaunchKernelGGL(k_update_left<S>, dim3((unsigned)tot), dim3(64), lds_left, st, ua);
-        if ((rc = launch_check("k_update_left"))) return rc;
+        if ((rc = launch_check("k_update_left"))) return rc; }
+        // exact zeros of the structure after sweep j2
+        { ProfScope ps(4, st);
+        const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr);
+        hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0,
+                           (q + 4) * rr);
+        if ((rc = launch_check("k_clean"))) return rc; }
     }
     if ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
     return 0;
@@ -235,6 +322,32 @@ const char *ht_strerror(int code)
 const char *ht_version(void) { return "libht 0.1 (gfx950)"; }
 
 const char *ht_last_error_message(void) { return ht::g_errmsg; }
+
+int ht_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(ht::g_prof_mu);
+    ht::g_prof_on = on != 0;
+    return 0;
+}
+
+int ht_profile_read(double *ms, int64_t *count, int nclasses)
+{
+    std::vector<ht::ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(ht::g_prof_mu);
+        recs.swap(ht::g_prof);
+    }
+    for (int c = 0; c < nclasses; ++c) { if (ms) ms[c] = 0.0; if (count) count[c] = 0; }
+    int rc = 0;
+    for (auto &p : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&t, p.a, p.b) != hipSuccess) rc = HT_ERR_HIP;
+        if (p.cls < nclasses) { if (ms) ms[p.cls] += t; if (count) count[p.cls] += 1; }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    return rc;
+}
 
 }  // extern "C"
 

@@ -108,3 +108,44 @@ def test_invalid_arguments():
     assert ht.lib().ht_stage2(None, None, None, None, 4, 2, 2, None) == -7
     assert ht.lib().ht_stage2(None, None, None, None, 4, 2, 4, None) == -1
     assert ht.lib().ht_stage2_q(ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(H.data_ptr()), None, None, 8, 2, 8, 3, None) == -8
+
+
+@pytest.mark.parametrize("n,r,q", [(1100, 8, 8), (1030, 16, 16), (700, 8, 4)])
+def test_parity_many_windows(n, r, q):
+    """Regression: more than ~64 windows per group with q = r once amplified
+    rounding residue left in structurally-zero entries between groups."""
+    H, T = inputs.rht_pencil(n, r, 0)
+    check_parity(H, T, r, q)
+
+
+def _backward(Hin, Tin, r, q=0):
+    ht = _ht()
+    n = Hin.shape[0]
+    H0 = ht.colmajor(Hin)
+    T0 = ht.colmajor(Tin)
+    Hd, Td = H0.clone(), T0.clone()
+    Qd = torch.eye(n, dtype=H0.dtype, device=H0.device).t().contiguous().t()
+    Zd = Qd.clone()
+    ht.stage2(Hd, Td, r, Qd, Zd, q=q)
+    torch.cuda.synchronize()
+    I = torch.eye(n, dtype=H0.dtype, device=H0.device)
+    res = {
+        "orthQ": torch.linalg.norm(Qd.conj().t() @ Qd - I).item(),
+        "orthZ": torch.linalg.norm(Zd.conj().t() @ Zd - I).item(),
+        "bH": (torch.linalg.norm(Qd @ Hd @ Zd.conj().t() - H0) / torch.linalg.norm(H0)).item(),
+        "bT": (torch.linalg.norm(Qd @ Td @ Zd.conj().t() - T0) / torch.linalg.norm(T0)).item(),
+        "zeros": bool((torch.tril(Hd, -2) == 0).all().item() and (torch.tril(Td, -1) == 0).all().item()),
+    }
+    return res
+
+
+@pytest.mark.parametrize("n,r", [(2048, 8), (4096, 16)])
+def test_backward_error_large(n, r):
+    """Invariants at sizes the oracle is too slow for: exact zeros, orthogonality and
+    backward error within 100 n eps (eps = 2^-52)."""
+    print(f"[backward] n={n} r={r}", flush=True)
+    H, T = inputs.rht_pencil(n, r, 1)
+    res = _backward(H, T, r)
+    bound = 100 * n * EPS
+    assert res["zeros"], res
+    assert max(res["orthQ"], res["orthZ"], res["bH"], res["bT"]) <= bound, (res, bound)

@@ -33,11 +33,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def counted_flops_by_class(n, r):
-    """Algorithmic flops of the unblocked algorithm, split by where the blocked
-    implementation performs them: right-type applications (H, T, Z by the
-    right reflectors; Q by the left ones) and left-type (rows of H and T)."""
+    """Algorithmic flops of the unblocked algorithm, split by the kernel class
+    of the blocked implementation that performs them: right updates of H and T
+    (rows 1..i3 of H, 1..i2 of T), updates of Q and Z (all n rows each) and
+    left updates of H and T (columns jb+1..n of H, i1..n of T)."""
     import numpy as np
-    right = left = 0.0
+    right = qz = left = 0.0
     for j in range(1, n - 1):
         nb = 1 + (n - j - 2) // r
         k = np.arange(nb, dtype=np.int64)
@@ -46,9 +47,10 @@ def counted_flops_by_class(n, r):
         i2 = np.minimum(j + (k + 1) * r, n)
         i3 = np.minimum(j + (k + 2) * r, n)
         m = (i2 - i1 + 1).astype(np.float64)
-        right += float(np.sum(4.0 * m * (i3 + i2 + 2.0 * n)))
+        right += float(np.sum(4.0 * m * (i3 + i2)))
+        qz += float(np.sum(4.0 * m * 2.0 * n))
         left += float(np.sum(4.0 * m * ((n - jb) + (n - i1 + 1))))
-    return right, left
+    return {"update_right": right, "update_qz": qz, "update_left": left}
 
 
 def cpu_baseline(H, T, r, target_s=15.0):
@@ -131,16 +133,17 @@ def main():
     value = total_flops * K / elapsed / 1e9
 
     # roofline of the dominant kernel class (algorithmic flops per launch / mean launch time)
-    fr, fl = counted_flops_by_class(n, r)
-    per_class_flops = {"update_right": fr, "update_left": fl}
-    dom = max(("update_right", "update_left", "generate"), key=lambda c: prof[c][0])
+    per_class_flops = counted_flops_by_class(n, r)
+    dom = max(("update_right", "update_left", "update_qz", "generate"), key=lambda c: prof[c][0])
     ms_tot, launches = prof[dom]
+    kernel_names = {"update_right": "k_update_right_reg<double>", "update_left": "k_update_left_reg<double>",
+                    "update_qz": "k_update_right_reg<double> (Q, Z)"}
     if dom in per_class_flops and launches > 0:
         per_launch = per_class_flops[dom] * K / launches
         achieved = per_launch / (ms_tot / launches * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                    "kernel": f"k_update_{dom.split('_')[1]}<double>",
+                    "kernel": kernel_names[dom],
                     "algorithmic_flops_per_launch": per_launch,
                     "mean_launch_ms": round(ms_tot / launches, 4)}
     else:

@@ -13,6 +13,10 @@ namespace ht {
 // ------------------------------------------------------------------ scalars
 struct zd { double re, im; };
 
+// branch-free choice, component-wise for complex values
+__host__ __device__ inline double sel(bool c, double a, double b) { return c ? a : b; }
+__host__ __device__ inline zd sel(bool c, zd a, zd b) { zd z; z.re = c ? a.re : b.re; z.im = c ? a.im : b.im; return z; }
+
 __host__ __device__ inline double re(double a) { return a; }
 __host__ __device__ inline double re(zd a) { return a.re; }
 __host__ __device__ inline double im(double) { return 0.0; }

@@ -85,6 +85,8 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
     __shared__ S blk[32 * LB];
     __shared__ S yb[32 * LB];
     __shared__ S stau[4];
+    __shared__ S lzv[kMaxR * kMaxR];            // staged lazy reflectors (sweeps j1..j-1, block k)
+    __shared__ S lzt[kMaxR];
 
     for (int64_t k = 0; k < kext; ++k) {
         if (w > 0) {
@@ -113,7 +115,18 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         const int64_t i3 = i64min(j + (k + 2) * r, n);
         const bool full = k < nbj;
 
-        // ---- 1. lazy left updates (wave 0: H column jb, wave 1: T column i1+r-1)
+        // ---- 1. lazy left updates (wave 0: H column jb, wave 1: T column i1+r-1);
+        // the reflectors of block k of the earlier sweeps are first staged in
+        // LDS with one parallel round trip
+        if (j > j1) {
+            const int nw = (int)(j - j1);
+            for (int e = tid; e < nw * r; e += 256) {
+                const int wh = e / (int)r, ii = e % (int)r;
+                lzv[e] = a.VL[(wh * kext + k) * r + ii];
+            }
+            for (int e = tid; e < nw; e += 256) lzt[e] = a.TL[e * kext + k];
+            __syncthreads();
+        }
         if (wid < 2 && j > j1) {
             const bool isH = (wid == 0);
             const int64_t col = isH ? jb : i1 + r - 1;          // 1-based
@@ -126,12 +139,12 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 S x = inr ? X[B.idx(row - 1, col - 1)] : zero<S>();
                 for (int64_t jh = j1; jh < j; ++jh) {
                     const int64_t wh = jh - j1;
-                    const S tau = a.TL[wh * kext + k];
+                    const S tau = lzt[wh];
                     if (iszero(tau)) continue;                  // block (jh,k) absent or trivial
                     const int64_t aa = jh + k * r + 1;
                     const int64_t bb = i64min(jh + (k + 1) * r, n);
                     const bool inb = row >= aa && row <= bb;
-                    const S vi = inb ? a.VL[(wh * kext + k) * r + (row - aa)] : zero<S>();
+                    const S vi = inb ? lzv[wh * r + (row - aa)] : zero<S>();
                     S s = wave_sum(cmul(vi, x));
                     s = mul(conj_(tau), s);
                     if (inb) x = sub(x, mul(s, vi));

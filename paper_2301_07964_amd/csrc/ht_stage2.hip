@@ -12,12 +12,14 @@
 #include "ht_common.hpp"
 #include "ht_generate.hpp"
 #include "ht_update.hpp"
+#include "ht_update_reg.hpp"
 #include "ht_workspace.hpp"
 #include "ht.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -37,9 +39,9 @@ int launch_check(const char *what)
 // ------------------------------------------------------------ profiling
 // When enabled, every kernel launch of stage two is bracketed by HIP events
 // recorded on the caller's stream; ht_profile_read() sums the elapsed times
-// per kernel class.  Classes: 0 band copy, 1 generate, 2 right update,
-// 3 left update, 4 zeroing.
-constexpr int kProfClasses = 5;
+// per kernel class.  Classes: 0 band copy, 1 generate, 2 right update of H
+// and T, 3 left update, 4 exact zeros, 5 right update of Q and Z.
+constexpr int kProfClasses = 6;
 struct ProfRec { int cls; hipEvent_t a, b; };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
@@ -144,10 +146,71 @@ static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st)
 
 inline int64_t default_q(int64_t n, int64_t r) { (void)n; return r; }
 
+// Reflector buffers: the Q/Z updates of group g run on an auxiliary stream
+// while the caller's stream goes on with group g+1, so consecutive groups use
+// different buffers.
+constexpr int kNBuf = 2;
+
+// Auxiliary stream and events per (device, caller stream).
+struct AuxCtx {
+    hipStream_t aux = nullptr;
+    hipEvent_t gen[kNBuf] = {}, qz[kNBuf] = {}, join = nullptr;
+    bool ok = false;
+};
+static std::mutex g_aux_mu;
+static std::map<std::pair<int, hipStream_t>, AuxCtx> g_aux;
+
+static AuxCtx *aux_ctx(hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    AuxCtx &c = g_aux[{dev, st}];
+    if (c.ok) return &c;
+    if (hipStreamCreateWithFlags(&c.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    for (int b = 0; b < kNBuf; ++b) {
+        if (hipEventCreateWithFlags(&c.gen[b], hipEventDisableTiming) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&c.qz[b], hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    if (hipEventCreateWithFlags(&c.join, hipEventDisableTiming) != hipSuccess) return nullptr;
+    c.ok = true;
+    return &c;
+}
+
+// Launch the application-phase kernels: register-ring variants for r in
+// {4, 8, 16, 32} (complex: up to 16), the LDS-ring kernels otherwise.
+template <class S>
+static int launch_update(bool right, const UpdArgs<S> &ua, int64_t panels, hipStream_t st)
+{
+    const int64_t r = ua.r;
+    const bool cplx = sizeof(S) > 8;
+    const dim3 g((unsigned)panels), blk(64);
+#define HT_REG_CASE(RR)                                                                               \
+    case RR:                                                                                          \
+        if (right) hipLaunchKernelGGL((k_update_right_reg<S, RR>), g, blk, 0, st, ua);               \
+        else hipLaunchKernelGGL((k_update_left_reg<S, RR>), g, blk, 0, st, ua);                      \
+        return launch_check(right ? "k_update_right_reg" : "k_update_left_reg");
+    if (!(cplx && r > 16)) {
+        switch (r) {
+            HT_REG_CASE(4)
+            HT_REG_CASE(8)
+            HT_REG_CASE(16)
+            HT_REG_CASE(32)
+            default: break;
+        }
+    }
+#undef HT_REG_CASE
+    const size_t lds_right = (size_t)(2 * r) * 64 * sizeof(S);
+    const size_t lds_left = lds_right + (size_t)64 * 65 * sizeof(S);
+    if (right) hipLaunchKernelGGL(k_update_right<S>, g, blk, lds_right, st, ua);
+    else hipLaunchKernelGGL(k_update_left<S>, g, blk, lds_left, st, ua);
+    return launch_check(right ? "k_update_right" : "k_update_left");
+}
+
 struct Geometry {
     int64_t n, r, q, kext, BU, BL, ldb;
     size_t esz;
-    size_t off_SH, off_ST, off_VL, off_VR, off_TL, off_TR, off_prog, total;
+    size_t off_SH, off_ST, off_refl, refl_bytes, off_prog, total;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -163,10 +226,8 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
     size_t o = 0;
     g.off_SH = o; o += al((size_t)n * g.ldb * esz);
     g.off_ST = o; o += al((size_t)n * g.ldb * esz);
-    g.off_VL = o; o += al((size_t)q * g.kext * r * esz);
-    g.off_VR = o; o += al((size_t)q * g.kext * r * esz);
-    g.off_TL = o; o += al((size_t)q * g.kext * esz);
-    g.off_TR = o; o += al((size_t)q * g.kext * esz);
+    g.refl_bytes = al((size_t)q * g.kext * r * esz) * 2 + al((size_t)q * g.kext * esz) * 2;
+    g.off_refl = o; o += g.refl_bytes * kNBuf;
     g.off_prog = o; o += al((size_t)q * sizeof(int));
     g.total = o;
     return g;
@@ -199,19 +260,26 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     unsigned char *ws = (unsigned char *)workspace_get(g.total, st, &rc);
     if (!ws) return rc;
     S *SH = (S *)(ws + g.off_SH), *ST = (S *)(ws + g.off_ST);
-    S *VL = (S *)(ws + g.off_VL), *VR = (S *)(ws + g.off_VR);
-    S *TL = (S *)(ws + g.off_TL), *TR = (S *)(ws + g.off_TR);
     int *prog = (int *)(ws + g.off_prog);
     const Band B{g.BU, g.BL, g.ldb};
     const int64_t rr = re_;
-    const size_t lds_right = (size_t)(2 * rr) * 64 * sizeof(S);
-    const size_t lds_left = lds_right + (size_t)64 * 65 * sizeof(S);
+    const bool qz = (Q != nullptr) || (Z != nullptr);
+    AuxCtx *ax = qz ? aux_ctx(st) : nullptr;
+    if (qz && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
+    const int64_t np = (n + 63) / 64;
 
-    for (int64_t j1 = 1; j1 <= n - 2; j1 += q) {
+    int64_t grp = 0;
+    for (int64_t j1 = 1; j1 <= n - 2; j1 += q, ++grp) {
         const int64_t j2 = i64min(j1 + q - 1, n - 2);
         const int64_t qg = j2 - j1 + 1;
         const int64_t kmax = nblocks(n, rr, j1);
         const int64_t kext = kmax + 1;
+        const int buf = (int)(grp % kNBuf);
+        unsigned char *rb = ws + g.off_refl + g.refl_bytes * buf;
+        const size_t vbytes = al((size_t)q * g.kext * rr * sizeof(S)), tbytes = al((size_t)q * g.kext * sizeof(S));
+        S *VL = (S *)rb, *VR = (S *)(rb + vbytes), *TL = (S *)(rb + 2 * vbytes), *TR = (S *)(rb + 2 * vbytes + tbytes);
+        // the aux stream must be done with this buffer (group grp - kNBuf)
+        if (qz && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
         // 1. scratch band
         { ProfScope ps(0, st);
         hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
@@ -224,11 +292,9 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         { ProfScope ps(1, st);
         hipLaunchKernelGGL(k_generate<S>, dim3((unsigned)qg), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
-        // 3. application: right updates
         UpdArgs<S> ua;
         ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;
         ua.VL = VL; ua.TL = TL; ua.VR = VR; ua.TR = TR;
-        const int64_t np = (n + 63) / 64;
         int nj = 0;
         int64_t tot = 0;
         auto addjob = [&](S *X, int side, int64_t lim) {
@@ -236,28 +302,39 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
             ua.job[nj].X = X; ua.job[nj].ld = ld; ua.job[nj].lim = lim; ua.job[nj].npanels = np; ua.job[nj].side = side;
             ++nj; tot += np;
         };
+        // 3a. Q and Z (right updates) on the auxiliary stream
+        if (qz) {
+            if (hipEventRecord(ax->gen[buf], st) != hipSuccess) return HT_ERR_HIP;
+            if (hipStreamWaitEvent(ax->aux, ax->gen[buf], 0) != hipSuccess) return HT_ERR_HIP;
+            addjob(Z, 1, -1);
+            addjob(Q, 0, -1);
+            ua.njobs = nj;
+            { ProfScope ps(5, ax->aux);
+            if ((rc = launch_update<S>(true, ua, tot, ax->aux))) return rc; }
+            if (hipEventRecord(ax->qz[buf], ax->aux) != hipSuccess) return HT_ERR_HIP;
+        }
+        // 3b. H and T: right updates, then left updates, then the exact zeros
+        nj = 0; tot = 0;
         addjob(H, 1, (q + 2) * rr);
         addjob(T, 1, (q + 1) * rr);
-        addjob(Z, 1, -1);
-        addjob(Q, 0, -1);
         ua.njobs = nj;
         { ProfScope ps(2, st);
-        hipLaunchKernelGGL(k_update_right<S>, dim3((unsigned)tot), dim3(64), lds_right, st, ua);
-        if ((rc = launch_check("k_update_right"))) return rc; }
-        // left updates of H and T
+        if ((rc = launch_update<S>(true, ua, tot, st))) return rc; }
         nj = 0; tot = 0;
         addjob(H, 0, (q + 1) * rr);
         addjob(T, 0, (q + 1) * rr);
         ua.njobs = nj;
         { ProfScope ps(3, st);
-        hipLaunchKernelGGL(k_update_left<S>, dim3((unsigned)tot), dim3(64), lds_left, st, ua);
-        if ((rc = launch_check("k_update_left"))) return rc; }
-        // exact zeros of the structure after sweep j2
+        if ((rc = launch_update<S>(false, ua, tot, st))) return rc; }
         { ProfScope ps(4, st);
         const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr);
         hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0,
                            (q + 4) * rr);
         if ((rc = launch_check("k_clean"))) return rc; }
+    }
+    if (qz) {   // join the auxiliary stream
+        if (hipEventRecord(ax->join, ax->aux) != hipSuccess) return HT_ERR_HIP;
+        if (hipStreamWaitEvent(st, ax->join, 0) != hipSuccess) return HT_ERR_HIP;
     }
     if ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
     return 0;

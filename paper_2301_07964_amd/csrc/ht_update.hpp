@@ -40,11 +40,12 @@ struct UpdArgs {
     int njobs;
 };
 
-// ring slot of local index c of window k (streaming from k = kmax-1 downwards)
+// ring slot of local index c (< 2r) of window k (streaming from k = kmax-1
+// downwards): windows advance by r and the ring has 2r slots, so only the
+// parity of the window count matters
 __device__ inline int ring_slot(int64_t k, int64_t kmax, int64_t r, int c, int rs) {
-    int64_t t = (kmax - 1 - k) * r;            // shift of window k relative to the first one
-    int64_t s = ((int64_t)c - t) % rs;
-    return (int)(s < 0 ? s + rs : s);
+    const int s = c - (int)(((kmax - 1 - k) & 1) * r);
+    return s < 0 ? s + rs : s;
 }
 
 // Right mode: X(rows, window) <- X(rows, window) * G_{j1} ... G_{j2}

@@ -24,6 +24,14 @@
 //      j1+1+(k-d) r), d = j2-j (T is skipped for the last sweep).
 // Reflectors (v, tau) are stored, zero padded to r entries, for the delayed
 // updates; tau = 0 marks a block that does not exist for that sweep.
+//
+// Latency is what matters here (the q workgroups form a pipeline whose pace
+// is set by the slowest step), so the two long loops keep their rows in
+// registers, with the block order RM >= r a compile-time constant: the RQ runs
+// in one wavefront, lane l holding row l of the block and lane 32+l row l of
+// the accumulated orthogonal factor, so that a step of the factorisation
+// only broadcasts the pivot row; the eager right updates load a whole row
+// segment before they write any of it back.
 #pragma once
 #include "ht_common.hpp"
 
@@ -69,7 +77,82 @@ __device__ inline void wave_larfg(S x, int lane, int m, S &v, S &tau, S &beta) {
     v = (lane == 0) ? one<S>() : mul(x, sc);
 }
 
-template <class S>
+// broadcast of lane l's value (l a compile-time constant after unrolling)
+__device__ inline double bcast(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline zd bcast(zd v, int l) { return mk<zd>(bcast(v.re, l), bcast(v.im, l)); }
+
+// Householder RQ of the m x m block held row-wise by one wavefront: lane l < m
+// holds row l of the block in x[0..m-1], lane 32 + l row l of Y (on entry the
+// identity).  Rows are processed from the last (step i annihilates entries
+// 0..i-1 of row i with a reflector acting on columns 0..i, xLARFG convention),
+// every reflector is applied to the block rows and to Y, so that on exit
+// Y = Q^H and column 0 of Y (x[0] of lanes 32..32+m-1) is the first row of
+// the orthogonal RQ factor, conjugated.
+template <class S, int RM>
+__device__ inline void rq_rows(S (&x)[RM], int m)
+{
+#pragma unroll
+    for (int i = RM - 1; i >= 1; --i) {
+        if (i >= m) continue;
+        S b[RM];
+#pragma unroll
+        for (int c = 0; c <= i; ++c) b[c] = conj_(bcast(x[c], i));
+        const S alpha = b[i];
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < i; ++c) { if (c & 1) s1 += abs2(b[c]); else s0 += abs2(b[c]); }
+        const double ss = s0 + s1;
+        if (ss == 0.0 && im(alpha) == 0.0) continue;              // tau = 0: identity
+        const double bb = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
+        const S tau = mk<S>((bb - re(alpha)) / bb, -im(alpha) / bb);
+        const S sc = recip(sub(alpha, mk<S>(bb, 0.0)));
+#pragma unroll
+        for (int c = 0; c < i; ++c) b[c] = mul(b[c], sc);          // u_c; u_i = 1
+        S d0 = x[i], d1 = zero<S>();
+#pragma unroll
+        for (int c = 0; c < i; ++c) { if (c & 1) d1 = add(d1, mul(x[c], b[c])); else d0 = add(d0, mul(x[c], b[c])); }
+        const S sv = mul(add(d0, d1), tau);
+#pragma unroll
+        for (int c = 0; c < i; ++c) x[c] = sub(x[c], mul(sv, conj_(b[c])));
+        x[i] = sub(x[i], sv);
+    }
+}
+
+// rows [top, bot] (1-based) of the band copy X, columns i1 .. i1+m-1:
+// X <- X (I - sig w w^H); each row segment is loaded completely before any of
+// it is written back.
+template <class S, int RM>
+__device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
+                                  const S *sw, S sig, int tid)
+{
+    const int64_t cs = B.ldb - 1;                  // stride between columns of one band row
+    for (int64_t row = top + tid; row <= bot; row += 256) {
+        S *p = X + B.idx(row - 1, i1 - 1);
+        S x[RM];
+#pragma unroll
+        for (int c = 0; c < RM; ++c) {
+            x[c] = zero<S>();
+            if (c < m) x[c] = p[c * cs];
+        }
+        S d0 = zero<S>(), d1 = zero<S>();
+#pragma unroll
+        for (int c = 0; c < RM; c += 2) {
+            d0 = add(d0, mul(x[c], sw[c]));
+            d1 = add(d1, mul(x[c + 1], sw[c + 1]));
+        }
+        const S sx = mul(add(d0, d1), sig);
+#pragma unroll
+        for (int c = 0; c < RM; ++c)
+            if (c < m) p[c * cs] = sub(x[c], mul(sx, conj_(sw[c])));
+    }
+}
+
+template <class S, int RM>
 __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 {
     const int w = blockIdx.x;
@@ -83,7 +166,6 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
     constexpr int LB = 33;                       // LDS leading dimension of 32x32 blocks
     __shared__ S sv[64], sw[64], su[64];
     __shared__ S blk[32 * LB];
-    __shared__ S yb[32 * LB];
     __shared__ S stau[4];
     __shared__ S lzv[kMaxR * kMaxR];            // staged lazy reflectors (sweeps j1..j-1, block k)
     __shared__ S lzt[kMaxR];
@@ -195,52 +277,23 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             for (int e = tid; e < m * m; e += 256) {
                 const int ii = e % m, cc = e / m;
                 ST[B.idx(i1 - 1 + ii, i1 - 1 + cc)] = blk[cc * LB + ii];
-                yb[cc * LB + ii] = (ii == cc) ? one<S>() : zero<S>();
             }
             __syncthreads();
 
-            // ---- 3. RQ of the block (last row first) on [blk; I]
-            for (int i = m - 1; i >= 1; --i) {
-                if (wid == 0) {
-                    S b = lane <= i ? conj_(blk[lane * LB + i]) : zero<S>();
-                    // xLARFG with alpha = b_i, x = b_0..b_{i-1}
-                    S alpha = shfl_(b, i);
-                    double ss = wave_sum(lane < i ? abs2(b) : 0.0);
-                    S tau, u;
-                    if (ss == 0.0 && im(alpha) == 0.0) {
-                        tau = zero<S>();
-                        u = zero<S>();
-                    } else {
-                        double bb = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
-                        tau = mk<S>((bb - re(alpha)) / bb, -im(alpha) / bb);
-                        S sc = recip(sub(alpha, mk<S>(bb, 0.0)));
-                        u = lane < i ? mul(b, sc) : (lane == i ? one<S>() : zero<S>());
-                    }
-                    if (lane <= i) su[lane] = u;
-                    if (lane == 0) stau[1] = tau;
-                }
-                __syncthreads();
-                const S tau = stau[1];
-                if (!iszero(tau)) {
-                    // rows 0..i-1 of blk and rows 0..m-1 of yb: X(row, 0:i) <- X (I - tau u u^H)
-                    const int rr = tid >> 2, sub4 = tid & 3;
-                    S *X = nullptr;
-                    int row = 0;
-                    if (rr < i) { X = blk; row = rr; }
-                    else if (rr < i + m) { X = yb; row = rr - i; }
-                    S part = zero<S>();
-                    if (X)
-                        for (int c = sub4; c <= i; c += 4) part = add(part, mul(X[c * LB + row], su[c]));
-                    S s = group_sum<4>(part);
-                    s = mul(s, tau);
-                    if (X)
-                        for (int c = sub4; c <= i; c += 4) X[c * LB + row] = sub(X[c * LB + row], mul(s, conj_(su[c])));
-                }
-                __syncthreads();
-            }
-            // ---- normalise y = Y(:,0) and generate the opposite reflector
+            // ---- 3. RQ of the block (last row first) on [blk; I], in registers
             if (wid == 0) {
-                S y = lane < m ? yb[lane] : zero<S>();
+                S x[RM];
+#pragma unroll
+                for (int c = 0; c < RM; ++c) {
+                    S v = zero<S>();
+                    if (lane < m && c < m) v = blk[c * LB + lane];
+                    if (lane == 32 + c && c < m) v = one<S>();
+                    x[c] = v;
+                }
+                rq_rows<S, RM>(x, m);
+                // ---- normalise y = Y(:,0) and generate the opposite reflector
+                S y = shfl_(x[0], 32 + (lane & 31));
+                if (lane >= m) y = zero<S>();
                 unsigned long long mask = __ballot(lane < m && !iszero(y));
                 const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
                 S yp = shfl_(y, p);
@@ -256,11 +309,8 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 }
                 S v, tau, beta;
                 wave_larfg(y, lane, m, v, tau, beta);
-                if (lane < r) {
-                    S vs = lane < m ? v : zero<S>();
-                    a.VR[(w * kext + k) * r + lane] = vs;
-                    sw[lane] = vs;
-                }
+                if (lane < r) a.VR[(w * kext + k) * r + lane] = lane < m ? v : zero<S>();
+                if (lane < RM) sw[lane] = lane < m ? v : zero<S>();
                 if (lane == 0) { a.TR[w * kext + k] = tau; stau[2] = tau; }
             }
             __syncthreads();
@@ -270,26 +320,10 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             if (!iszero(sig)) {
                 const int64_t d = j2 - j;
                 const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
-                for (int64_t row = topH + tid; row <= i3; row += 256) {
-                    S s = zero<S>();
-                    for (int c = 0; c < m; ++c) s = add(s, mul(SH[B.idx(row - 1, i1 - 1 + c)], sw[c]));
-                    s = mul(s, sig);
-                    for (int c = 0; c < m; ++c) {
-                        S *p = SH + B.idx(row - 1, i1 - 1 + c);
-                        *p = sub(*p, mul(s, conj_(sw[c])));
-                    }
-                }
+                right_rows<S, RM>(SH, B, topH, i3, i1, m, sw, sig, tid);
                 if (d >= 1) {
                     const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
-                    for (int64_t row = topT + tid; row <= i2; row += 256) {
-                        S s = zero<S>();
-                        for (int c = 0; c < m; ++c) s = add(s, mul(ST[B.idx(row - 1, i1 - 1 + c)], sw[c]));
-                        s = mul(s, sig);
-                        for (int c = 0; c < m; ++c) {
-                            S *p = ST + B.idx(row - 1, i1 - 1 + c);
-                            *p = sub(*p, mul(s, conj_(sw[c])));
-                        }
-                    }
+                    right_rows<S, RM>(ST, B, topT, i2, i1, m, sw, sig, tid);
                 }
             }
             __syncthreads();

@@ -290,7 +290,9 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
         ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
         { ProfScope ps(1, st);
-        hipLaunchKernelGGL(k_generate<S>, dim3((unsigned)qg), dim3(256), 0, st, ga);
+        if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)qg), dim3(256), 0, st, ga);
+        else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)qg), dim3(256), 0, st, ga);
+        else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)qg), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
         UpdArgs<S> ua;
         ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;

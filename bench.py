@@ -160,13 +160,15 @@ def main():
     # the application kernels stream every entry they update once per group
     # (q/4 flop per byte, below the FP64 ridge 78.6/8 = 9.8): HBM bound
     per_class_bytes = update_bytes_by_class(n, r, q)
-    kernels = {"k_update_right_reg<double>": ("update_right", "update_qz"),
-               "k_update_left_reg<double>": ("update_left",),
+    mfma = r in (4, 8, 16, 32)
+    kernels = {("k_update_mfma<right>" if mfma else "k_update_right_reg<double>"): ("update_right", "update_qz"),
+               ("k_update_mfma<left>" if mfma else "k_update_left_reg<double>"): ("update_left",),
                "k_generate<double>": ("generate",)}
     ktime = {kn: sum(prof[c][0] for c in cl) for kn, cl in kernels.items()}
     klaunch = {kn: sum(prof[c][1] for c in cl) for kn, cl in kernels.items()}
     dom = max(ktime, key=ktime.get)
     if dom != "k_generate<double>" and klaunch[dom] > 0:
+        # FP64 matrix-core and vector peaks are equal on MI355X (78.6 TFLOP/s)
         per_launch_b = sum(per_class_bytes[c] for c in kernels[dom]) * K / klaunch[dom]
         per_launch_f = sum(per_class_flops[c] for c in kernels[dom]) * K / klaunch[dom]
         mean_s = ktime[dom] / klaunch[dom] * 1e-3

@@ -146,7 +146,8 @@ const char *ht_last_error_message(void);
  * ms[0..nclasses-1] / count[0..nclasses-1] (either may be NULL) and forgets
  * the records.  Classes: 0 band copy, 1 generate, 2 right update of H and T,
  * 3 left update of H and T, 4 exact-zero passes, 5 update of Q and Z (runs on
- * a second stream, concurrently with classes 2-4).  Returns 0 or HT_ERR_HIP.
+ * a second stream, concurrently with classes 2-4), 6 accumulation of the
+ * window factors.  Returns 0 or HT_ERR_HIP.
  */
 int ht_profile_enable(int on);
 int ht_profile_read(double *ms, int64_t *count, int nclasses);

@@ -72,7 +72,7 @@ EXPORTS = (
     "ht_profile_enable", "ht_profile_read",
 )
 
-PROFILE_CLASSES = ("band_copy", "generate", "update_right", "update_left", "zeroing", "update_qz")
+PROFILE_CLASSES = ("band_copy", "generate", "update_right", "update_left", "zeroing", "update_qz", "form_factors")
 
 
 def profile_enable(on: bool = True):

@@ -13,6 +13,7 @@
 #include "ht_generate.hpp"
 #include "ht_update.hpp"
 #include "ht_update_reg.hpp"
+#include "ht_update_mfma.hpp"
 #include "ht_workspace.hpp"
 #include "ht.h"
 
@@ -40,8 +41,9 @@ int launch_check(const char *what)
 // When enabled, every kernel launch of stage two is bracketed by HIP events
 // recorded on the caller's stream; ht_profile_read() sums the elapsed times
 // per kernel class.  Classes: 0 band copy, 1 generate, 2 right update of H
-// and T, 3 left update, 4 exact zeros, 5 right update of Q and Z.
-constexpr int kProfClasses = 6;
+// and T, 3 left update, 4 exact zeros, 5 right update of Q and Z, 6 window
+// factors.
+constexpr int kProfClasses = 7;
 struct ProfRec { int cls; hipEvent_t a, b; };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
@@ -207,11 +209,71 @@ static int launch_update(bool right, const UpdArgs<S> &ua, int64_t panels, hipSt
     return launch_check(right ? "k_update_right" : "k_update_left");
 }
 
+// Matrix-core application kernels (real, r in {4, 8, 16, 32}).  Each job's
+// npanels counts wavefront tiles of 16*TRW rows (right) / columns (left).
+template <int R>
+static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, hipStream_t st)
+{
+    const int trw = ua.n >= 8192 ? 2 : 1;
+    const int64_t tile = 16 * trw;
+    int64_t tot = 0;
+    for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + tile - 1) / tile; tot += ua.job[i].npanels; }
+    const dim3 grid((unsigned)((tot + 3) / 4)), blk(256);
+    if (trw == 2) {
+        if (left) hipLaunchKernelGGL((k_update_mfma<R, 2, true>), grid, blk, 0, st, ua, F);
+        else hipLaunchKernelGGL((k_update_mfma<R, 2, false>), grid, blk, 0, st, ua, F);
+    } else {
+        if (left) hipLaunchKernelGGL((k_update_mfma<R, 1, true>), grid, blk, 0, st, ua, F);
+        else hipLaunchKernelGGL((k_update_mfma<R, 1, false>), grid, blk, 0, st, ua, F);
+    }
+    return launch_check(left ? "k_update_mfma(left)" : "k_update_mfma(right)");
+}
+
+static int launch_update_mfma(bool left, const UpdArgs<double> &ua, const double *F, hipStream_t st)
+{
+    switch (ua.r) {
+    case 4: return launch_update_mfma_r<4>(left, ua, F, st);
+    case 8: return launch_update_mfma_r<8>(left, ua, F, st);
+    case 16: return launch_update_mfma_r<16>(left, ua, F, st);
+    case 32: return launch_update_mfma_r<32>(left, ua, F, st);
+    default: return HT_ERR_NOTSUP;
+    }
+}
+
+static int launch_form_factors(int64_t r, int64_t q, int64_t kmax, int64_t kext, const double *VL, const double *TL,
+                               const double *VR, const double *TR, double *F, hipStream_t st)
+{
+    const dim3 grid((unsigned)kmax, 2), blk(64);
+    switch (r) {
+    case 4: hipLaunchKernelGGL((k_form_factors<4, 16>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 8: hipLaunchKernelGGL((k_form_factors<8, 16>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 16: hipLaunchKernelGGL((k_form_factors<16, 32>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 32: hipLaunchKernelGGL((k_form_factors<32, 64>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    default: return HT_ERR_NOTSUP;
+    }
+    return launch_check("k_form_factors");
+}
+
+// dispatch of one update pass: matrix cores for real r in {4, 8, 16, 32},
+// the vector kernels otherwise
+template <class S>
+static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S *F, hipStream_t st)
+{
+    if constexpr (sizeof(S) == 8) {
+        if (F) return launch_update_mfma(!right, ua, (const double *)F, st);
+    }
+    return launch_update<S>(right, ua, panels, st);
+}
+
 struct Geometry {
     int64_t n, r, q, kext, BU, BL, ldb;
     size_t esz;
-    size_t off_SH, off_ST, off_refl, refl_bytes, off_prog, total;
+    size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, off_prog, total;
 };
+
+// The matrix-core application path: real arithmetic, r in {4, 8, 16, 32}.
+static bool use_mfma(int64_t r, size_t esz) { return esz == 8 && (r == 4 || r == 8 || r == 16 || r == 32); }
+static int64_t kw_of(int64_t r) { return 2 * r < 16 ? 16 : 2 * r; }
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -226,7 +288,12 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
     size_t o = 0;
     g.off_SH = o; o += al((size_t)n * g.ldb * esz);
     g.off_ST = o; o += al((size_t)n * g.ldb * esz);
-    g.refl_bytes = al((size_t)q * g.kext * r * esz) * 2 + al((size_t)q * g.kext * esz) * 2;
+    // per buffer: V_L, V_R, tau_L, tau_R and, on the matrix-core path, the
+    // window factors of both sides
+    g.vbytes = al((size_t)q * g.kext * r * esz);
+    g.tbytes = al((size_t)q * g.kext * esz);
+    g.refl_bytes = g.vbytes * 2 + g.tbytes * 2;
+    if (use_mfma(r, esz)) g.refl_bytes += al((size_t)2 * g.kext * kw_of(r) * kw_of(r) * esz);
     g.off_refl = o; o += g.refl_bytes * kNBuf;
     g.off_prog = o; o += al((size_t)q * sizeof(int));
     g.total = o;
@@ -267,6 +334,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     AuxCtx *ax = qz ? aux_ctx(st) : nullptr;
     if (qz && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
     const int64_t np = (n + 63) / 64;
+    const bool mf = use_mfma(rr, sizeof(S));
 
     int64_t grp = 0;
     for (int64_t j1 = 1; j1 <= n - 2; j1 += q, ++grp) {
@@ -276,8 +344,9 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         const int64_t kext = kmax + 1;
         const int buf = (int)(grp % kNBuf);
         unsigned char *rb = ws + g.off_refl + g.refl_bytes * buf;
-        const size_t vbytes = al((size_t)q * g.kext * rr * sizeof(S)), tbytes = al((size_t)q * g.kext * sizeof(S));
+        const size_t vbytes = g.vbytes, tbytes = g.tbytes;
         S *VL = (S *)rb, *VR = (S *)(rb + vbytes), *TL = (S *)(rb + 2 * vbytes), *TR = (S *)(rb + 2 * vbytes + tbytes);
+        S *F = mf ? (S *)(rb + 2 * vbytes + 2 * tbytes) : nullptr;    // window factors
         // the aux stream must be done with this buffer (group grp - kNBuf)
         if (qz && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
         // 1. scratch band
@@ -294,6 +363,12 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)qg), dim3(256), 0, st, ga);
         else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)qg), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
+        if constexpr (sizeof(S) == 8) {
+            if (mf) {
+                ProfScope ps(6, st);
+                if ((rc = launch_form_factors(rr, qg, kmax, kext, VL, TL, VR, TR, F, st))) return rc;
+            }
+        }
         UpdArgs<S> ua;
         ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;
         ua.VL = VL; ua.TL = TL; ua.VR = VR; ua.TR = TR;
@@ -312,7 +387,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
             addjob(Q, 0, -1);
             ua.njobs = nj;
             { ProfScope ps(5, ax->aux);
-            if ((rc = launch_update<S>(true, ua, tot, ax->aux))) return rc; }
+            if ((rc = launch_pass<S>(true, ua, tot, F, ax->aux))) return rc; }
             if (hipEventRecord(ax->qz[buf], ax->aux) != hipSuccess) return HT_ERR_HIP;
         }
         // 3b. H and T: right updates, then left updates, then the exact zeros
@@ -321,13 +396,13 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         addjob(T, 1, (q + 1) * rr);
         ua.njobs = nj;
         { ProfScope ps(2, st);
-        if ((rc = launch_update<S>(true, ua, tot, st))) return rc; }
+        if ((rc = launch_pass<S>(true, ua, tot, F, st))) return rc; }
         nj = 0; tot = 0;
         addjob(H, 0, (q + 1) * rr);
         addjob(T, 0, (q + 1) * rr);
         ua.njobs = nj;
         { ProfScope ps(3, st);
-        if ((rc = launch_update<S>(false, ua, tot, st))) return rc; }
+        if ((rc = launch_pass<S>(false, ua, tot, F, st))) return rc; }
         { ProfScope ps(4, st);
         const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr);
         hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0,

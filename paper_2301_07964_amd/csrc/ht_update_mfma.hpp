@@ -1,0 +1,198 @@
+// ht_update_mfma.hpp -- application phase of blocked stage two on the FP64
+// matrix cores (Section 3.2, "Applying the reflectors"; application algorithm
+// of the appendix), real arithmetic, r in {4, 8, 16, 32}.
+//
+// The q reflectors of window k (local indices 0 .. W-1, W = q+r-1, the w-th
+// reflector acting on w .. w+r-1) are first accumulated into the window's
+// orthogonal factor U_k = G_0 G_1 ... G_{q-1}, embedded in the identity of
+// order KW = max(16, 2r) (k_form_factors).  Right updates then compute
+// X(:, window) <- X(:, window) U_k and left updates X(window, :) <-
+// U_k^H X(window, :), as the paper's delayed updates do with its window
+// factors, windows from the bottom (k = kmax-1) to the top.
+//
+// MFMA formulation (v_mfma_f64_16x16x4f64: D = A B + C with A 16x4, B 4x16;
+// lane l holds A[l%16][l/16], B[l/16][l%16] and D[4v + l/16][l%16], v < 4):
+//   right:  D^T = U^T X^T  for a tile of 16 rows of X,
+//   left:   D   = U^T X    for a tile of 16 columns (real case: U^H = U^T),
+// so in both cases A is a fragment of U^T and B holds the tile with lane l
+// on row/column l%16 and window index 4kk + l/16 in register kk.  The result
+// lands with window index 16mb + 4v + l/16 in register (mb, v) of lane l,
+// which is exactly where the B operand of the next step wants index
+// 4(4mb+v) + l/16: the window ring stays in registers without any exchange.
+// Consecutive windows overlap in q-1 indices (local c of window k is local
+// c + r of window k-1), so the carried registers shift by r/4.
+#pragma once
+#include "ht_common.hpp"
+#include "ht_update.hpp"
+
+namespace ht {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// order of the embedded window factor for block size R
+template <int R> struct KWOf { static constexpr int value = (2 * R < 16) ? 16 : 2 * R; };
+
+// Window factors.  Grid (kmax, 2): blockIdx.y = 0 uses the left reflectors,
+// 1 the right reflectors; one wavefront per window, lane i computes row i of
+// U_k.  Output: F[(side*kext + k)*KW*KW + (mb*KK + kk)*64 + l]
+//             = U_k[4kk + l/16][16mb + l%16]   (the A fragments of U_k^T).
+template <int R, int KW>
+__global__ __launch_bounds__(64) void k_form_factors(int64_t q, int64_t kext, const double *VL, const double *TL,
+                                                     const double *VR, const double *TR, double *F)
+{
+    constexpr int MB = KW / 16, KK = KW / 4;
+    const int64_t k = blockIdx.x;
+    const int side = blockIdx.y;
+    const int lane = threadIdx.x;
+    const double *V = side ? VR : VL;
+    const double *Tv = side ? TR : TL;
+    double u[KW];
+#pragma unroll
+    for (int c = 0; c < KW; ++c) u[c] = (c == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int w = 0; w < R; ++w) {
+        if (w < q) {
+            const double tau = Tv[w * kext + k];
+            if (tau != 0.0) {
+                const double *v = V + (w * kext + k) * R;
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < R; c += 2) {
+                    s0 += u[w + c] * v[c];
+                    s1 += u[w + c + 1] * v[c + 1];
+                }
+                const double s = (s0 + s1) * tau;
+#pragma unroll
+                for (int c = 0; c < R; ++c) u[w + c] -= s * v[c];
+            }
+        }
+    }
+    __shared__ double tr[KW][KW + 1];
+    if (lane < KW) {
+#pragma unroll
+        for (int c = 0; c < KW; ++c) tr[lane][c] = u[c];
+    }
+    __syncthreads();
+    double *out = F + ((int64_t)side * kext + k) * (KW * KW);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+            out[(mb * KK + kk) * 64 + lane] = tr[4 * kk + (lane >> 4)][16 * mb + (lane & 15)];
+}
+
+// Delayed updates on the matrix cores.  256 threads = 4 independent
+// wavefronts; each owns TRW tiles of 16 rows (right) or 16 columns (left) of
+// one job's matrix and streams them through the windows.  Jobs: as for the
+// vector kernels (UpdJob), with npanels counted in wavefront tiles of 16*TRW.
+template <int R, int TRW, bool LEFT>
+__global__ __launch_bounds__(256) void k_update_mfma(UpdArgs<double> a, const double *F)
+{
+    constexpr int KW = KWOf<R>::value;
+    constexpr int MB = KW / 16, KK = KW / 4, RS = R / 4;
+    const int lane = threadIdx.x & 63;
+    int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int jid = 0;
+    while (jid < a.njobs - 1 && b >= a.job[jid].npanels) { b -= a.job[jid].npanels; ++jid; }
+    UpdJob<double> J = a.job[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
+    if (b >= J.npanels) return;
+    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
+    const int64_t W = q + R - 1;
+    const int g = lane >> 4, li = lane & 15;
+    const int64_t p0 = b * (16 * TRW);              // first row (right) / column (left) of the tiles
+    const double *Fs = F + (LEFT ? 0 : (int64_t)J.side * kext * (KW * KW));
+    double *X = J.X;
+    const int64_t ld = J.ld;
+
+    // windows this wavefront has to apply (same limits as the vector kernels)
+    int64_t kfirst = kmax - 1, klast = 0;
+    if (J.lim >= 0) {
+        if (!LEFT) {
+            while (klast < kmax && !(p0 < i64min(j1 + klast * R + W - 1, n - 1) + 1 + J.lim)) ++klast;
+            if (klast >= kmax) return;
+        } else {
+            while (kfirst >= 0 && !(p0 + 16 * TRW > j1 + kfirst * R - J.lim)) --kfirst;
+            if (kfirst < 0) return;
+        }
+    }
+    // element (tile t, window index c) of window starting at lo
+    auto addr = [&](int t, int64_t lo, int c, bool &ok) -> int64_t {
+        const int64_t fixed = p0 + 16 * t + li, idx = lo + c;
+        ok = fixed < n && idx < n;
+        return LEFT ? idx + fixed * ld : fixed + idx * ld;
+    };
+
+    double xb[TRW][KK];
+    {
+        const int64_t lo = j1 + kfirst * R;
+#pragma unroll
+        for (int t = 0; t < TRW; ++t)
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int c = 4 * kk + g;
+                bool ok;
+                const int64_t ad = addr(t, lo, c, ok);
+                double v = 0.0;
+                if (ok && c < W) v = X[ad];
+                xb[t][kk] = v;
+            }
+    }
+    for (int64_t k = kfirst; k >= klast; --k) {
+        const int64_t lo = j1 + k * R;
+        const double *Fk = Fs + k * (KW * KW);
+        f64x4 acc[TRW][MB];
+#pragma unroll
+        for (int t = 0; t < TRW; ++t)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            double af[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) af[mb] = Fk[(mb * KK + kk) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int t = 0; t < TRW; ++t)
+                    acc[t][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], xb[t][kk], acc[t][mb], 0, 0, 0);
+        }
+        // finished indices go back to HBM
+        const int64_t f0 = (k == klast) ? 0 : q - 1;
+#pragma unroll
+        for (int t = 0; t < TRW; ++t)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 16 * mb + 4 * v + g;
+                    bool ok;
+                    const int64_t ad = addr(t, lo, c, ok);
+                    if (ok && c >= f0 && c < W) X[ad] = acc[t][mb][v];
+                }
+        if (k == klast) break;
+        // carry local 0 .. q-2 to local r .. W-1 of window k-1, load its new
+        // indices 0 .. r-1
+        const int64_t lon = lo - R;
+#pragma unroll
+        for (int t = 0; t < TRW; ++t) {
+#pragma unroll
+            for (int kk = 0; kk < RS; ++kk) {
+                const int c = 4 * kk + g;
+                xb[t][kk + RS] = (c < q - 1) ? acc[t][kk >> 2][kk & 3] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < RS; ++kk) {
+                const int c = 4 * kk + g;
+                bool ok;
+                const int64_t ad = addr(t, lon, c, ok);
+                double v = 0.0;
+                if (ok) v = X[ad];
+                xb[t][kk] = v;
+            }
+        }
+    }
+}
+
+}  // namespace ht

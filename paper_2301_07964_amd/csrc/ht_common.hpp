@@ -53,19 +53,39 @@ __host__ __device__ inline zd recip(zd z) {
 }
 
 // ------------------------------------------------------- wave reductions
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Cross-lane data movement with DPP (in-row permutations, no LDS round trip)
+// and v_readlane (broadcast of one lane into scalar registers).
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffu), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
-__device__ inline zd wave_sum(zd v) { return mk<zd>(wave_sum(v.re), wave_sum(v.im)); }
-// sum over aligned groups of G lanes (G power of two <= 64)
+// value of lane l in every lane (l wave-uniform)
+__device__ __forceinline__ double bcast(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ zd bcast(zd v, int l) { return mk<zd>(bcast(v.re, l), bcast(v.im, l)); }
+
+// sum over aligned groups of G lanes (G in {2, 4, 8, 16}), result in every
+// lane of the group: quad permutations, then half-row and row mirrors
 template <int G> __device__ inline double group_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += dpp_d<0xB1>(v);                              // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_d<0x4E>(v);                  // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_d<0x141>(v);                 // row_half_mirror
+    if (G >= 16) v += dpp_d<0x140>(v);                // row_mirror
     return v;
 }
 template <int G> __device__ inline zd group_sum(zd v) { return mk<zd>(group_sum<G>(v.re), group_sum<G>(v.im)); }
+// sum over the 64 lanes, result in every lane
+__device__ inline double wave_sum(double v) {
+    v = group_sum<16>(v);
+    return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+__device__ inline zd wave_sum(zd v) { return mk<zd>(wave_sum(v.re), wave_sum(v.im)); }
 
 // ------------------------------------------------------- stage-two index map
 // 1-based formulas of the unblocked stage-two algorithm.

@@ -62,7 +62,7 @@ __device__ inline void st_release(int *p, int v) {
 // Returns v_l (v_0 = 1), tau and beta in every lane.
 template <class S>
 __device__ inline void wave_larfg(S x, int lane, int m, S &v, S &tau, S &beta) {
-    S alpha = shfl_(x, 0);
+    const S alpha = bcast(x, 0);
     double ss = wave_sum((lane >= 1 && lane < m) ? abs2(x) : 0.0);
     if (ss == 0.0 && im(alpha) == 0.0) {
         tau = zero<S>();
@@ -77,22 +77,15 @@ __device__ inline void wave_larfg(S x, int lane, int m, S &v, S &tau, S &beta) {
     v = (lane == 0) ? one<S>() : mul(x, sc);
 }
 
-// broadcast of lane l's value (l a compile-time constant after unrolling)
-__device__ inline double bcast(double v, int l) {
-    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ inline zd bcast(zd v, int l) { return mk<zd>(bcast(v.re, l), bcast(v.im, l)); }
-
 // Householder RQ of the m x m block held row-wise by one wavefront: lane l < m
 // holds row l of the block in x[0..m-1], lane 32 + l row l of Y (on entry the
 // identity).  Rows are processed from the last (step i annihilates entries
 // 0..i-1 of row i with a reflector acting on columns 0..i, xLARFG convention),
 // every reflector is applied to the block rows and to Y, so that on exit
 // Y = Q^H and column 0 of Y (x[0] of lanes 32..32+m-1) is the first row of
-// the orthogonal RQ factor, conjugated.
+// the orthogonal RQ factor, conjugated.  The pivot row is broadcast into
+// scalar registers; each lane's product with it is formed while the norm,
+// square root and divisions of the reflector are in flight.
 template <class S, int RM>
 __device__ inline void rq_rows(S (&x)[RM], int m)
 {
@@ -102,23 +95,30 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
         S b[RM];
 #pragma unroll
         for (int c = 0; c <= i; ++c) b[c] = conj_(bcast(x[c], i));
-        const S alpha = b[i];
-        double s0 = 0.0, s1 = 0.0;
+        // p = sum_{c<i} x_c b_c (per lane) and ||b_{0..i-1}||^2 (uniform)
+        S p0 = zero<S>(), p1 = zero<S>();
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int c = 0; c < i; ++c) { if (c & 1) s1 += abs2(b[c]); else s0 += abs2(b[c]); }
-        const double ss = s0 + s1;
+        for (int c = 0; c < i; ++c) {
+            if (c & 1) p1 = add(p1, mul(x[c], b[c])); else p0 = add(p0, mul(x[c], b[c]));
+            switch (c & 3) {
+                case 0: s0 += abs2(b[c]); break;
+                case 1: s1 += abs2(b[c]); break;
+                case 2: s2 += abs2(b[c]); break;
+                default: s3 += abs2(b[c]); break;
+            }
+        }
+        const S alpha = b[i];
+        const double ss = (s0 + s1) + (s2 + s3);
         if (ss == 0.0 && im(alpha) == 0.0) continue;              // tau = 0: identity
         const double bb = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
         const S tau = mk<S>((bb - re(alpha)) / bb, -im(alpha) / bb);
-        const S sc = recip(sub(alpha, mk<S>(bb, 0.0)));
+        const S sc = recip(sub(alpha, mk<S>(bb, 0.0)));          // u_c = b_c sc (c < i), u_i = 1
+        // s = (x_i + sum_{c<i} x_c u_c) tau;  x_c -= s conj(u_c) = (s conj(sc)) conj(b_c)
+        const S sv = mul(add(x[i], mul(add(p0, p1), sc)), tau);
+        const S t = mul(sv, conj_(sc));
 #pragma unroll
-        for (int c = 0; c < i; ++c) b[c] = mul(b[c], sc);          // u_c; u_i = 1
-        S d0 = x[i], d1 = zero<S>();
-#pragma unroll
-        for (int c = 0; c < i; ++c) { if (c & 1) d1 = add(d1, mul(x[c], b[c])); else d0 = add(d0, mul(x[c], b[c])); }
-        const S sv = mul(add(d0, d1), tau);
-#pragma unroll
-        for (int c = 0; c < i; ++c) x[c] = sub(x[c], mul(sv, conj_(b[c])));
+        for (int c = 0; c < i; ++c) x[c] = sub(x[c], mul(t, conj_(b[c])));
         x[i] = sub(x[i], sv);
     }
 }
@@ -202,11 +202,20 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         // LDS with one parallel round trip
         if (j > j1) {
             const int nw = (int)(j - j1);
-            for (int e = tid; e < nw * r; e += 256) {
-                const int wh = e / (int)r, ii = e % (int)r;
-                lzv[e] = a.VL[(wh * kext + k) * r + ii];
+            constexpr int NV = (kMaxR * kMaxR + 255) / 256;      // fixed trip count: loads in flight together
+            S tv[NV];
+#pragma unroll
+            for (int it = 0; it < NV; ++it) {
+                const int e = tid + 256 * it;
+                tv[it] = zero<S>();
+                if (e < nw * r) tv[it] = a.VL[((e / (int)r) * kext + k) * r + e % (int)r];
             }
-            for (int e = tid; e < nw; e += 256) lzt[e] = a.TL[e * kext + k];
+            if (tid < nw) lzt[tid] = a.TL[tid * kext + k];
+#pragma unroll
+            for (int it = 0; it < NV; ++it) {
+                const int e = tid + 256 * it;
+                if (e < nw * r) lzv[e] = tv[it];
+            }
             __syncthreads();
         }
         if (wid < 2 && j > j1) {
@@ -257,9 +266,20 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 }
             }
             // T block -> LDS
-            for (int e = tid; e < m * m; e += 256) {
-                const int ii = e % m, cc = e / m;
-                blk[cc * LB + ii] = ST[B.idx(i1 - 1 + ii, i1 - 1 + cc)];
+            {
+                constexpr int NB = (32 * 32 + 255) / 256;
+                S tb[NB];
+#pragma unroll
+                for (int it = 0; it < NB; ++it) {
+                    const int e = tid + 256 * it, ii = e % m, cc = e / m;
+                    tb[it] = zero<S>();
+                    if (e < m * m) tb[it] = ST[B.idx(i1 - 1 + ii, i1 - 1 + cc)];
+                }
+#pragma unroll
+                for (int it = 0; it < NB; ++it) {
+                    const int e = tid + 256 * it, ii = e % m, cc = e / m;
+                    if (e < m * m) blk[cc * LB + ii] = tb[it];
+                }
             }
             __syncthreads();
             {   // apply G^H to the block: 8 lanes per column
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 if (lane >= m) y = zero<S>();
                 unsigned long long mask = __ballot(lane < m && !iszero(y));
                 const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
-                S yp = shfl_(y, p);
+                const S yp = bcast(y, p);
                 if (!iszero(yp)) {
                     const double aa = sqrt(abs2(yp));
                     if (im(yp) == 0.0) {

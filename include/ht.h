@@ -83,14 +83,21 @@ int ht_stage2_z_q(void *H, void *T, void *Q, void *Z,
                   int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
 
 /*
- * ht_stage2_batched -- `count` independent stage-two reductions in one
- * persistent launch (pencils of uneven n and r).  H, T, Q, Z, n, r, ld, q are
- * HOST arrays of length `count` (Q[b] / Z[b] may be NULL; q[b] = 0 selects the
- * built-in choice; the q array itself may be NULL); they are copied before the
- * call returns.  Each pencil's arithmetic is identical to a single
- * ht_stage2_q call with the same (n, r, q).
- * Errors: -1 count < 0, -2..-5 NULL array, -6 n array, -7 r array,
- * -8 ld array (first offending entry decides), -9 q array.
+ * ht_stage2_batched -- `count` independent stage-two reductions (pencils of
+ * uneven n and r, each as ht_stage2 defines it) in ONE persistent launch:
+ * every workgroup takes whole pencils from a device-side queue and chases
+ * their bulges with the unblocked algorithm of the appendix (Section 3.1),
+ * each reflector applied at once to its full range.  The reflectors are
+ * those of ht_stage2, so the results agree with it up to rounding.  Meant
+ * for many small pencils (n up to about a thousand), where the latency of
+ * the sweep steps, not flops, bounds the time.
+ *   H, T, Q, Z, n, r, ld, q are HOST arrays of length `count`; Q[b] / Z[b]
+ *   may be NULL; q may be NULL (q[b] is validated like ht_stage2_q's q and
+ *   otherwise unused: the unblocked chase has no group size).  The arrays are
+ *   read before the call returns.  The matrices must not overlap.
+ * Errors: -1 count < 0, -2..-5 NULL array (or NULL H[b]/T[b] with n[b] > 0),
+ * -6 n array, -7 r array, -8 ld array, -9 q array (first offending entry
+ * decides); HT_ERR_NOTSUP for min(r, n-1) > 32.
  */
 int ht_stage2_batched(int64_t count, double *const *H, double *const *T,
                       double *const *Q, double *const *Z, const int64_t *n,

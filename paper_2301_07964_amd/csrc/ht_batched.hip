@@ -1,0 +1,253 @@
+// ht_batched.hip -- batched stage two: many independent r-HT pencils of
+// uneven n and r reduced to Hessenberg-triangular form in ONE persistent
+// launch (the C ABI ht_stage2_batched / ht_stage2_batched_z).
+//
+// Small pencils (the batched workloads have n of a few hundred) are bound by
+// the latency of the ~n^2/(2r) dependent steps of the sweep chase, not by
+// flops, so a launch per group and phase (the blocked single-pencil path) is
+// the wrong shape for them.  Here each workgroup of 256 threads pulls whole
+// pencils from a device-side queue (a vector atomic on a counter) and runs
+// the unblocked stage-two algorithm of the appendix on it (Section 3.1):
+// for every sweep j and block k,
+//   wavefront 0: left reflector from H(i1:i2, jb) (xLARFG),
+//   all threads: G^H applied to rows i1..i2 of H (columns jb+1..n) and T
+//                (columns i1..n), Q <- Q G on columns i1..i2,
+//   wavefront 0: RQ of the updated T block in registers, opposite reflector,
+//   all threads: W applied to columns i1..i2 of H (rows 1..i3), T (rows
+//                1..i2) and Z (all rows); T(i1+1:i2, i1) <- 0 exactly.
+// Every reflector is applied to its full range immediately, as in the
+// unblocked algorithm, so the results agree with ht_stage2 up to rounding.
+#include "ht_common.hpp"
+#include "ht_generate.hpp"
+#include "ht_workspace.hpp"
+#include "ht.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+
+namespace ht {
+
+extern thread_local char g_errmsg[256];
+int launch_check(const char *what);
+
+template <class S>
+struct Pencil {
+    S *H, *T, *Q, *Z;
+    int64_t n, r, ld;
+};
+
+constexpr int kBatThreads = 256;
+
+__global__ void k_reset_counter(int *c) { if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0; }
+
+// X(rows a..a+m-1, cols c0..c1) <- G^H X, one column per thread
+template <class S>
+__device__ inline void left_cols(S *X, int64_t ld, int64_t a, int m, int64_t c0, int64_t c1,
+                                 const S *v, S tau, int tid)
+{
+    const S ct = conj_(tau);
+    for (int64_t c = c0 + tid; c <= c1; c += kBatThreads) {
+        S *col = X + a + c * ld;
+        S s0 = zero<S>(), s1 = zero<S>();
+        int i = 0;
+        for (; i + 1 < m; i += 2) { s0 = add(s0, cmul(v[i], col[i])); s1 = add(s1, cmul(v[i + 1], col[i + 1])); }
+        if (i < m) s0 = add(s0, cmul(v[i], col[i]));
+        const S s = mul(ct, add(s0, s1));
+        for (int ii = 0; ii < m; ++ii) col[ii] = sub(col[ii], mul(s, v[ii]));
+    }
+}
+
+// X(rows r0..r1, cols a..a+m-1) <- X G, one row per thread; with zfirst the
+// entry of column a is written as an exact zero for rows > a
+template <class S>
+__device__ inline void right_rows_b(S *X, int64_t ld, int64_t a, int m, int64_t r0, int64_t r1,
+                                    const S *v, S tau, int tid, bool zfirst)
+{
+    for (int64_t row = r0 + tid; row <= r1; row += kBatThreads) {
+        S *p = X + row + a * ld;
+        S s0 = zero<S>(), s1 = zero<S>();
+        int c = 0;
+        for (; c + 1 < m; c += 2) { s0 = add(s0, mul(p[c * ld], v[c])); s1 = add(s1, mul(p[(c + 1) * ld], v[c + 1])); }
+        if (c < m) s0 = add(s0, mul(p[c * ld], v[c]));
+        const S s = mul(add(s0, s1), tau);
+        for (int cc = 0; cc < m; ++cc)
+            p[cc * ld] = (zfirst && cc == 0 && row > a) ? zero<S>() : sub(p[cc * ld], mul(s, conj_(v[cc])));
+    }
+}
+
+template <class S, int RM>
+__global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<S> *pen, int count, int *counter)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ S sv[64], sw[64];
+    __shared__ S stau[2];
+    __shared__ int s_idx;
+    for (;;) {
+        if (tid == 0) s_idx = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int b = s_idx;
+        __syncthreads();
+        if (b >= count) return;
+        const Pencil<S> P = pen[b];
+        const int64_t n = P.n, ld = P.ld;
+        S *H = P.H, *T = P.T, *Q = P.Q, *Z = P.Z;
+        const int64_t r = i64min(P.r, i64max(n - 1, 1));
+        // entries outside the r-HT pattern are not read: they become exact zeros
+        for (int64_t c = 0; c < n; ++c) {
+            for (int64_t i = c + r + 1 + tid; i < n; i += kBatThreads) H[i + c * ld] = zero<S>();
+            for (int64_t i = c + 1 + tid; i < n; i += kBatThreads) T[i + c * ld] = zero<S>();
+        }
+        __syncthreads();
+        if (n > 2 && r > 1) {
+            for (int64_t j = 1; j <= n - 2; ++j) {
+                const int64_t nbj = nblocks(n, r, j);
+                for (int64_t k = 0; k < nbj; ++k) {
+                    const int64_t jb = j + i64max(0, (k - 1) * r + 1);
+                    const int64_t i1 = j + k * r + 1;
+                    const int64_t i2 = i64min(j + (k + 1) * r, n);
+                    const int64_t i3 = i64min(j + (k + 2) * r, n);
+                    const int m = (int)(i2 - i1 + 1);
+                    const int64_t a = i1 - 1, cb = jb - 1;
+                    // left reflector
+                    if (wid == 0) {
+                        const S x = lane < m ? H[a + lane + cb * ld] : zero<S>();
+                        S v, tau, beta;
+                        wave_larfg(x, lane, m, v, tau, beta);
+                        sv[lane] = lane < m ? v : zero<S>();
+                        if (lane == 0) { stau[0] = tau; H[a + cb * ld] = beta; }
+                        else if (lane < m) H[a + lane + cb * ld] = zero<S>();
+                    }
+                    __syncthreads();
+                    {
+                        const S tau = stau[0];
+                        if (!iszero(tau)) {
+                            left_cols(H, ld, a, m, cb + 1, n - 1, sv, tau, tid);
+                            left_cols(T, ld, a, m, a, n - 1, sv, tau, tid);
+                            if (Q) right_rows_b(Q, ld, a, m, 0, n - 1, sv, tau, tid, false);
+                        }
+                    }
+                    __syncthreads();
+                    // RQ of the T block and the opposite reflector
+                    if (wid == 0) {
+                        S x[RM];
+#pragma unroll
+                        for (int c = 0; c < RM; ++c) {
+                            S v = zero<S>();
+                            if (lane < m && c < m) v = T[a + lane + (a + c) * ld];
+                            if (lane == 32 + c && c < m) v = one<S>();
+                            x[c] = v;
+                        }
+                        rq_rows<S, RM>(x, m);
+                        S y = shfl_(x[0], 32 + (lane & 31));
+                        if (lane >= m) y = zero<S>();
+                        const unsigned long long mask = __ballot(lane < m && !iszero(y));
+                        const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
+                        const S yp = bcast(y, p);
+                        if (!iszero(yp)) {
+                            const double aa = sqrt(abs2(yp));
+                            if (im(yp) == 0.0) {
+                                if (re(yp) < 0.0) y = mk<S>(-re(y), -im(y));
+                            } else {
+                                const S ph = mk<S>(re(yp) / aa, -im(yp) / aa);
+                                y = mul(y, ph);
+                                if (lane == p) y = mk<S>(re(y), 0.0);
+                            }
+                        }
+                        S v, tau, beta;
+                        wave_larfg(y, lane, m, v, tau, beta);
+                        sw[lane] = lane < m ? v : zero<S>();
+                        if (lane == 0) stau[1] = tau;
+                    }
+                    __syncthreads();
+                    {
+                        const S sig = stau[1];
+                        if (!iszero(sig)) {
+                            right_rows_b(H, ld, a, m, 0, i3 - 1, sw, sig, tid, false);
+                            right_rows_b(T, ld, a, m, 0, i2 - 1, sw, sig, tid, true);
+                            if (Z) right_rows_b(Z, ld, a, m, 0, n - 1, sw, sig, tid, false);
+                        } else {
+                            for (int64_t i = a + 1 + tid; i < a + m; i += kBatThreads) T[i + a * ld] = zero<S>();
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        // exact zeros of the output contract
+        for (int64_t c = 0; c < n; ++c) {
+            for (int64_t i = c + 2 + tid; i < n; i += kBatThreads) H[i + c * ld] = zero<S>();
+            for (int64_t i = c + 1 + tid; i < n; i += kBatThreads) T[i + c * ld] = zero<S>();
+        }
+        __syncthreads();
+    }
+}
+
+template <class S>
+static int batched_impl(int64_t count, S *const *H, S *const *T, S *const *Q, S *const *Z, const int64_t *n,
+                        const int64_t *r, const int64_t *ld, const int64_t *q, void *stream)
+{
+    if (count < 0) return -1;
+    if (count > 0 && !H) return -2;
+    if (count > 0 && !T) return -3;
+    if (count > 0 && !Q) return -4;
+    if (count > 0 && !Z) return -5;
+    if (count > 0 && !n) return -6;
+    if (count > 0 && !r) return -7;
+    if (count > 0 && !ld) return -8;
+    if (count == 0) return 0;
+    if (count > (int64_t)(1 << 30)) return -1;
+    std::vector<Pencil<S>> hp((size_t)count);
+    int64_t rmax = 1;
+    for (int64_t b = 0; b < count; ++b) {
+        if (n[b] < 0) return -6;
+        if (r[b] < 1) return -7;
+        if (ld[b] < (n[b] > 1 ? n[b] : 1)) return -8;
+        if (n[b] > 0 && (!H[b] || !T[b])) return -2;
+        if (q && (q[b] < 0 || (n[b] > 2 && q[b] > i64min(r[b], n[b] - 1)))) return -9;
+        hp[b] = Pencil<S>{H[b], T[b], Q[b], Z[b], n[b], r[b], ld[b]};
+        if (n[b] > 2) rmax = i64max(rmax, i64min(r[b], n[b] - 1));
+    }
+    if (rmax > kMaxR) return HT_ERR_NOTSUP;
+    hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();
+    g_errmsg[0] = 0;
+    int rc = 0;
+    const size_t dbytes = (size_t)count * sizeof(Pencil<S>);
+    const size_t dal = (dbytes + 255) & ~(size_t)255;
+    unsigned char *ws = (unsigned char *)workspace_get(dal + 256, st, &rc);
+    if (!ws) return rc;
+    Pencil<S> *dp = (Pencil<S> *)ws;
+    int *counter = (int *)(ws + dal);              // work queue position
+    // the descriptors are copied before the call returns (pageable source)
+    if (hipMemcpyAsync(dp, hp.data(), dbytes, hipMemcpyHostToDevice, st) != hipSuccess) return HT_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HT_ERR_HIP;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    if ((rc = launch_check("k_reset_counter"))) return rc;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) ncu = pr.multiProcessorCount;
+    }
+    const int64_t wgs = i64min(count, (int64_t)ncu * (rmax <= 16 ? 2 : 1));
+    const dim3 grid((unsigned)wgs), blk(kBatThreads);
+    if (rmax <= 16) hipLaunchKernelGGL((k_stage2_persistent<S, 16>), grid, blk, 0, st, dp, (int)count, counter);
+    else hipLaunchKernelGGL((k_stage2_persistent<S, 32>), grid, blk, 0, st, dp, (int)count, counter);
+    return launch_check("k_stage2_persistent");
+}
+
+}  // namespace ht
+
+extern "C" {
+int ht_stage2_batched(int64_t count, double *const *H, double *const *T, double *const *Q, double *const *Z,
+                      const int64_t *n, const int64_t *r, const int64_t *ld, const int64_t *q, void *stream)
+{
+    return ht::batched_impl<double>(count, H, T, Q, Z, n, r, ld, q, stream);
+}
+int ht_stage2_batched_z(int64_t count, void *const *H, void *const *T, void *const *Q, void *const *Z,
+                        const int64_t *n, const int64_t *r, const int64_t *ld, const int64_t *q, void *stream)
+{
+    return ht::batched_impl<ht::zd>(count, (ht::zd *const *)H, (ht::zd *const *)T, (ht::zd *const *)Q,
+                                    (ht::zd *const *)Z, n, r, ld, q, stream);
+}
+}

@@ -4,12 +4,6 @@
 #include <stdint.h>
 
 extern "C" {
-int ht_stage2_batched(int64_t, double *const *, double *const *, double *const *, double *const *,
-                      const int64_t *, const int64_t *, const int64_t *, const int64_t *, void *)
-{ return HT_ERR_NOTSUP; }
-int ht_stage2_batched_z(int64_t, void *const *, void *const *, void *const *, void *const *,
-                        const int64_t *, const int64_t *, const int64_t *, const int64_t *, void *)
-{ return HT_ERR_NOTSUP; }
 int ht_rhess(double *, double *, double *, double *, int64_t, int64_t, int64_t, void *) { return HT_ERR_NOTSUP; }
 int ht_rhess_z(void *, void *, void *, void *, int64_t, int64_t, int64_t, void *) { return HT_ERR_NOTSUP; }
 }

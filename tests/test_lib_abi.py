@@ -59,3 +59,29 @@ def test_argument_errors_need_no_device():
     assert f(None, None, None, None, 4, 2, 3, None) == -7
     assert f(None, None, None, None, 4, 2, 4, None) == -1
     assert f(None, None, None, None, 0, 2, 1, None) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")
+def test_batched_argument_errors_need_no_device():
+    """ht_stage2_batched validates its host arrays before any HIP call."""
+    L = ctypes.CDLL(LIB)
+    f = L.ht_stage2_batched
+    P = ctypes.POINTER(ctypes.c_void_p)
+    I = ctypes.POINTER(ctypes.c_int64)
+    f.argtypes = [ctypes.c_int64, P, P, P, P, I, I, I, I, ctypes.c_void_p]
+    cnt = 2
+    dummy = (ctypes.c_void_p * cnt)(16, 32)      # never dereferenced on the host
+    nul = (ctypes.c_void_p * cnt)(None, None)
+    arr = lambda *v: (ctypes.c_int64 * cnt)(*v)
+    ok = dict(n=arr(8, 9), r=arr(2, 3), ld=arr(8, 9), q=arr(0, 0))
+    def call(count=cnt, H=dummy, T=dummy, n=None, r=None, ld=None, q=None):
+        return f(count, H, T, nul, nul, n or ok["n"], r or ok["r"], ld or ok["ld"], q or ok["q"], None)
+    assert f(-1, None, None, None, None, None, None, None, None, None) == -1
+    assert f(0, None, None, None, None, None, None, None, None, None) == 0
+    assert f(cnt, None, dummy, nul, nul, ok["n"], ok["r"], ok["ld"], None, None) == -2
+    assert f(cnt, dummy, dummy, None, nul, ok["n"], ok["r"], ok["ld"], None, None) == -4
+    assert call(n=arr(8, -1)) == -6
+    assert call(r=arr(0, 3)) == -7
+    assert call(ld=arr(8, 4)) == -8
+    assert call(q=arr(0, 5)) == -9                 # q > min(r, n-1)
+    assert call(H=nul) == -2                        # NULL H[b] with n[b] > 0

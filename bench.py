@@ -91,6 +91,111 @@ def cpu_baseline(H, T, r, target_s=15.0):
             "sample": f"first {s} of {H.shape[0] - 2} sweeps of the same pencil (counted flops {fs:.3e}, {ts:.1f} s, 1 thread)"}
 
 
+def bench_batched(args):
+    """2048 independent r-HT pencils (n uniform on [32, 512], r in {4, 8, 16}
+    with r < n/4, Q and Z accumulated): one persistent ht_stage2_batched
+    launch vs a loop of single ht_stage2 calls (q from the autotune table) on
+    one stream.  Reports pencils/s of both and the p50/p99 completion time of
+    the pencils inside the persistent launch (device clock)."""
+    import numpy as np
+    import torch
+    import paper_2301_07964_amd as ht
+    from paper_2301_07964_amd import autotune, inputs
+
+    cnt = args.count
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = inputs.batch_configs(cnt, args.seed)
+    print(f"[bench] generating {cnt} pencils", file=sys.stderr, flush=True)
+    base = []
+    for b, (n, r) in enumerate(cfg):
+        H, T = inputs.rht_pencil(n, r, args.seed * 1000003 + b)
+        base.append((ht.colmajor(H, dev), ht.colmajor(T, dev), r))
+    flops = 0.0
+    for (n, r) in cfg:
+        flops += sum(counted_flops_by_class(n, r).values())
+
+    def fresh():
+        out = []
+        for H0, T0, r in base:
+            n = H0.shape[0]
+            I = torch.eye(n, dtype=torch.float64, device=dev).t()
+            out.append((H0.clone(memory_format=torch.preserve_format), T0.clone(memory_format=torch.preserve_format),
+                        I.clone(memory_format=torch.preserve_format), I.clone(memory_format=torch.preserve_format), r))
+        return out
+
+    stream = torch.cuda.current_stream()
+    # warm-up, then the timed persistent launch (kernel timing on for the stamps)
+    ht.stage2_batched(fresh()[:64], stream=stream)
+    torch.cuda.synchronize()
+    work = fresh()
+    torch.cuda.synchronize()
+    ht.profile_enable(True)
+    t0 = time.perf_counter()
+    ht.stage2_batched(work, stream=stream)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    ht.profile_enable(False)
+    done = np.array(ht.batched_completion_ms(cnt))
+    ht.profile_read()
+    print(f"[bench] persistent launch: {t_batched:.3f} s", file=sys.stderr, flush=True)
+
+    # invariants on every pencil of the batched run
+    worst = 0.0
+    eps = float(np.finfo(np.float64).eps)
+    ok = True
+    for (Hd, Td, Qd, Zd, r), (H0, T0, _) in zip(work, base):
+        n = Hd.shape[0]
+        I = torch.eye(n, dtype=torch.float64, device=dev)
+        e = max(torch.linalg.norm(Qd.t() @ Qd - I).item(), torch.linalg.norm(Zd.t() @ Zd - I).item(),
+                (torch.linalg.norm(Qd @ Hd @ Zd.t() - H0) / torch.linalg.norm(H0)).item(),
+                (torch.linalg.norm(Qd @ Td @ Zd.t() - T0) / torch.linalg.norm(T0)).item())
+        zeros = bool((torch.tril(Hd, -2) == 0).all().item() and (torch.tril(Td, -1) == 0).all().item())
+        ok = ok and zeros and e <= 100 * n * eps
+        worst = max(worst, e / (n * eps))
+    del work
+
+    # loop of single launches on one stream (autotuned q)
+    work = fresh()
+    torch.cuda.synchronize()
+    print(f"[bench] loop of {cnt} single launches", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i, (Hd, Td, Qd, Zd, r) in enumerate(work):
+        ht.stage2(Hd, Td, r, Qd, Zd, q=autotune.lookup(Hd.shape[0], r), stream=stream)
+        if (i + 1) % 512 == 0:
+            torch.cuda.synchronize()
+            print(f"[bench]   {i + 1} done, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    del work
+
+    out = {
+        "metric": "batched pencils/s (2048 r-HT pencils, one persistent launch) + p99 latency",
+        "value": round(cnt / t_batched, 1),
+        "unit": "pencils/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(t_batched * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cnt} independent r-HT pencils, n uniform on [32, 512], r in {{4, 8, 16}} with r < n/4, "
+                               f"Q and Z accumulated, seed {args.seed}", "count": cnt},
+        "counted_gflops_per_s": round(flops / t_batched / 1e9, 2),
+        "loop_of_single_launches": {"pencils_per_s": round(cnt / t_loop, 2), "seconds": round(t_loop, 3),
+                                    "q": "autotune table"},
+        "speedup_vs_loop": round(t_loop / t_batched, 2),
+        "completion_ms": {"p50": round(float(np.percentile(done, 50)), 3),
+                          "p99": round(float(np.percentile(done, 99)), 3),
+                          "max": round(float(done.max()), 3), "clock": "device wall clock, from the first pencil start"},
+        "check": {"ok": ok, "worst_error_over_n_eps": round(worst, 3), "bound_over_n_eps": 100},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,12 +208,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--workload", choices=("single", "batched"), default="single",
+                    help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch")
+    ap.add_argument("--count", type=int, default=2048, help="batched: number of pencils")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the reduction of one pencil is not sharded across devices).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import numpy as np
     import torch

@@ -159,6 +159,15 @@ const char *ht_last_error_message(void);
 int ht_profile_enable(int on);
 int ht_profile_read(double *ms, int64_t *count, int nclasses);
 
+/*
+ * Per-pencil completion times of the calling thread's last ht_stage2_batched
+ * call made while kernel timing was enabled: ms[b] = milliseconds from the
+ * earliest pencil start of that launch to the completion of pencil b, from the
+ * device wall clock.  `count` must equal that call's count.  Waits for the
+ * call's stream.  Returns 0, -1 (no such call or count mismatch) or HT_ERR_HIP.
+ */
+int ht_batched_completion_ms(double *ms, int64_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,8 @@ def lib(with_torch: bool = True):
     L.ht_release_workspace.restype = None
     L.ht_profile_enable.argtypes = [_int]
     L.ht_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), _PI, _int]
+    L.ht_batched_completion_ms.argtypes = [ctypes.POINTER(ctypes.c_double), _i64]
+    L.ht_batched_completion_ms.restype = _int
     _lib = L
     return L
 
@@ -69,7 +71,7 @@ EXPORTS = (
     "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_batched",
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_workspace_bytes",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
-    "ht_profile_enable", "ht_profile_read",
+    "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms",
 )
 
 PROFILE_CLASSES = ("band_copy", "generate", "update_right", "update_left", "zeroing", "update_qz", "form_factors")
@@ -208,6 +210,14 @@ def stage2_batched(pencils, q=None, stream=None):
     _check(f(cnt, *[ctypes.cast(a, _P) for a in arr], ctypes.cast(ns, _PI), ctypes.cast(rs, _PI),
              ctypes.cast(lds, _PI), ctypes.cast(qs, _PI), _stream_ptr(stream)), "ht_stage2_batched")
     return pencils
+
+
+def batched_completion_ms(count: int):
+    """Per-pencil completion times (ms from the first pencil start, device
+    clock) of the last batched call made with kernel timing enabled."""
+    ms = (ctypes.c_double * count)()
+    _check(lib().ht_batched_completion_ms(ms, count), "ht_batched_completion_ms")
+    return list(ms)
 
 
 def colmajor(x, device="cuda"):

@@ -30,6 +30,12 @@ namespace ht {
 
 extern thread_local char g_errmsg[256];
 int launch_check(const char *what);
+bool profiling_enabled();
+
+// per-pencil start/finish stamps of the last batched call made with kernel
+// timing enabled (device wall clock), per calling thread
+struct BatchStamps { unsigned long long *dev = nullptr; int64_t count = 0; hipStream_t st = nullptr; };
+static thread_local BatchStamps g_stamps;
 
 template <class S>
 struct Pencil {
@@ -77,7 +83,8 @@ __device__ inline void right_rows_b(S *X, int64_t ld, int64_t a, int m, int64_t 
 }
 
 template <class S, int RM>
-__global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<S> *pen, int count, int *counter)
+__global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<S> *pen, int count, int *counter,
+                                                                   unsigned long long *stamps)
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     __shared__ S sv[64], sw[64];
@@ -89,6 +96,7 @@ __global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<
         const int b = s_idx;
         __syncthreads();
         if (b >= count) return;
+        if (stamps && tid == 0) stamps[2 * b] = wall_clock64();
         const Pencil<S> P = pen[b];
         const int64_t n = P.n, ld = P.ld;
         S *H = P.H, *T = P.T, *Q = P.Q, *Z = P.Z;
@@ -180,6 +188,10 @@ __global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<
             for (int64_t i = c + 1 + tid; i < n; i += kBatThreads) T[i + c * ld] = zero<S>();
         }
         __syncthreads();
+        if (stamps && tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            stamps[2 * b + 1] = wall_clock64();
+        }
     }
 }
 
@@ -215,10 +227,14 @@ static int batched_impl(int64_t count, S *const *H, S *const *T, S *const *Q, S 
     int rc = 0;
     const size_t dbytes = (size_t)count * sizeof(Pencil<S>);
     const size_t dal = (dbytes + 255) & ~(size_t)255;
-    unsigned char *ws = (unsigned char *)workspace_get(dal + 256, st, &rc);
+    const bool timed = profiling_enabled();
+    const size_t sbytes = timed ? (size_t)count * 2 * sizeof(unsigned long long) : 0;
+    unsigned char *ws = (unsigned char *)workspace_get(dal + 256 + sbytes, st, &rc);
     if (!ws) return rc;
     Pencil<S> *dp = (Pencil<S> *)ws;
     int *counter = (int *)(ws + dal);              // work queue position
+    unsigned long long *stamps = timed ? (unsigned long long *)(ws + dal + 256) : nullptr;
+    g_stamps = BatchStamps{stamps, timed ? count : 0, st};
     // the descriptors are copied before the call returns (pageable source)
     if (hipMemcpyAsync(dp, hp.data(), dbytes, hipMemcpyHostToDevice, st) != hipSuccess) return HT_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return HT_ERR_HIP;
@@ -231,8 +247,8 @@ static int batched_impl(int64_t count, S *const *H, S *const *T, S *const *Q, S 
     }
     const int64_t wgs = i64min(count, (int64_t)ncu * (rmax <= 16 ? 2 : 1));
     const dim3 grid((unsigned)wgs), blk(kBatThreads);
-    if (rmax <= 16) hipLaunchKernelGGL((k_stage2_persistent<S, 16>), grid, blk, 0, st, dp, (int)count, counter);
-    else hipLaunchKernelGGL((k_stage2_persistent<S, 32>), grid, blk, 0, st, dp, (int)count, counter);
+    if (rmax <= 16) hipLaunchKernelGGL((k_stage2_persistent<S, 16>), grid, blk, 0, st, dp, (int)count, counter, stamps);
+    else hipLaunchKernelGGL((k_stage2_persistent<S, 32>), grid, blk, 0, st, dp, (int)count, counter, stamps);
     return launch_check("k_stage2_persistent");
 }
 
@@ -243,6 +259,23 @@ int ht_stage2_batched(int64_t count, double *const *H, double *const *T, double 
                       const int64_t *n, const int64_t *r, const int64_t *ld, const int64_t *q, void *stream)
 {
     return ht::batched_impl<double>(count, H, T, Q, Z, n, r, ld, q, stream);
+}
+int ht_batched_completion_ms(double *ms, int64_t count)
+{
+    const ht::BatchStamps b = ht::g_stamps;
+    if (!ms || count != b.count || !b.dev) return -1;
+    if (count == 0) return 0;
+    std::vector<unsigned long long> h((size_t)count * 2);
+    if (hipStreamSynchronize(b.st) != hipSuccess) return HT_ERR_HIP;
+    if (hipMemcpy(h.data(), b.dev, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+        return HT_ERR_HIP;
+    int dev = 0, rate_khz = 100000;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+    unsigned long long t0 = h[0];
+    for (int64_t i = 0; i < count; ++i) t0 = h[2 * i] < t0 ? h[2 * i] : t0;
+    for (int64_t i = 0; i < count; ++i) ms[i] = (double)(h[2 * i + 1] - t0) / (double)rate_khz;
+    return 0;
 }
 int ht_stage2_batched_z(int64_t count, void *const *H, void *const *T, void *const *Q, void *const *Z,
                         const int64_t *n, const int64_t *r, const int64_t *ld, const int64_t *q, void *stream)

@@ -47,6 +47,7 @@ constexpr int kProfClasses = 7;
 struct ProfRec { int cls; hipEvent_t a, b; };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+bool profiling_enabled() { std::lock_guard<std::mutex> lk(g_prof_mu); return g_prof_on; }
 static std::vector<ProfRec> g_prof;
 
 struct ProfScope {

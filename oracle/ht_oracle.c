@@ -416,3 +416,266 @@ double oracle_stage2_flops(int64_t n, int64_t r, int is_complex)
     }
     return is_complex ? 4.0 * fl : fl;
 }
+
+/* ======================================================================== */
+/* Stage one (Section 2.2; blocked stage-one algorithm of the appendix),     */
+/* preceded by the QR factorisation of B (the experiments of Section 4       */
+/* replace B by the R of its QR factorisation).  1-based index map:          */
+/*   panels j = 1, 1+nb, ... <= n-2 (nb = r), j2 = min(n, j+nb-1),           */
+/*   n_blocks = ceil((n-nb-j+1) / ((p-1) nb)), blocks k = n_blocks-1 .. 0:   */
+/*   i1 = j+nb+k(p-1)nb, i2 = min(n, i1+p nb-1).                             */
+/* Left: QR of A(i1:i2, j:j2) by Householder reflectors, each applied at     */
+/* once to A (the columns right of it), B (columns i1..n) and Q.  Right,     */
+/* per block from the bottom: RQ of B(i1:i2, i1:i2) = Rt Qt, LQ of the first */
+/* min(nb, i2-i1+1) rows of Qt by reflectors P_t applied from the right,     */
+/* Qt(1:nb,:) P_0 ... P_{nb-1} = L; the same P_t are applied to A (all rows),*/
+/* B (rows 1..i2) and Z, which makes the first nb columns of the B block     */
+/* upper triangular (written as exact zeros).  p >= 2.                       */
+/* ======================================================================== */
+
+/* Householder RQ of the m x m matrix W (modified): for i = m-1..1 a
+ * reflector U_i on columns 0..i maps row i to a multiple of e_i (the same
+ * reflectors as oracle_rq_dir_*); Y <- I U_{m-1} ... U_1, so that
+ * B = Rt Qt with Qt = Y^H. */
+static void rq_accum_d(int64_t m, double *W, double *Y, double *u)
+{
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t i = 0; i < m; ++i) Y[i + c * m] = (i == c) ? 1.0 : 0.0;
+    for (int64_t i = m - 1; i >= 1; --i) {
+        for (int64_t c = 0; c <= i; ++c) u[c] = W[i + c * m];
+        double alpha = u[i], tau;
+        oracle_larfg_d(i + 1, &alpha, u, &tau);
+        u[i] = 1.0;
+        if (tau == 0.0) continue;
+        for (int pass = 0; pass < 2; ++pass) {
+            double *X = pass ? Y : W;
+            int64_t rows = pass ? m : i;
+            for (int64_t rr = 0; rr < rows; ++rr) {
+                double s = 0.0;
+                for (int64_t c = 0; c <= i; ++c) s += X[rr + c * m] * u[c];
+                s *= tau;
+                for (int64_t c = 0; c <= i; ++c) X[rr + c * m] -= s * u[c];
+            }
+        }
+    }
+}
+
+static void rq_accum_z(int64_t m, zdbl *W, zdbl *Y, zdbl *u)
+{
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t i = 0; i < m; ++i) Y[i + c * m] = zmk(i == c ? 1.0 : 0.0, 0.0);
+    for (int64_t i = m - 1; i >= 1; --i) {
+        for (int64_t c = 0; c <= i; ++c) u[c] = zconj(W[i + c * m]);
+        zdbl alpha = u[i], tau;
+        oracle_larfg_z(i + 1, &alpha, u, &tau);
+        u[i] = zmk(1.0, 0.0);
+        if (tau.re == 0.0 && tau.im == 0.0) continue;
+        for (int pass = 0; pass < 2; ++pass) {
+            zdbl *X = pass ? Y : W;
+            int64_t rows = pass ? m : i;
+            for (int64_t rr = 0; rr < rows; ++rr) {
+                zdbl s = zmk(0.0, 0.0);
+                for (int64_t c = 0; c <= i; ++c) s = zadd(s, zmul(X[rr + c * m], u[c]));
+                s = zmul(s, tau);
+                for (int64_t c = 0; c <= i; ++c) X[rr + c * m] = zsub(X[rr + c * m], zmul(s, zconj(u[c])));
+            }
+        }
+    }
+}
+
+int oracle_rhess_d(int64_t n, int64_t r, int64_t p, double *A, double *B, double *Q, double *Z,
+                   int64_t ld, double *flops)
+{
+    if (n < 0) return -1;
+    if (r < 1) return -2;
+    if (p < 2) return -3;
+    if (ld < (n > 1 ? n : 1)) return -8;
+    if (n == 0) return 0;
+    const int64_t nb = r < n - 1 ? r : (n > 1 ? n - 1 : 1);
+    const int64_t mb = p * nb;                               /* largest block order */
+    double *v = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *W = (double *)malloc(sizeof(double) * (size_t)(mb * mb));
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(mb * mb));
+    double *M = (double *)malloc(sizeof(double) * (size_t)(nb * mb));
+    double *u = (double *)malloc(sizeof(double) * (size_t)(mb + 1));
+    if (!v || !W || !Y || !M || !u) { free(v); free(W); free(Y); free(M); free(u); return 1; }
+    double fl = 0.0;
+    /* QR of B: B = Q_B R, A <- Q_B^H A, Q <- Q Q_B */
+    for (int64_t c = 0; c + 1 < n; ++c) {
+        const int64_t m = n - c;
+        double alpha = B[c + c * ld], tau;
+        for (int64_t i = 1; i < m; ++i) v[i] = B[c + i + c * ld];
+        oracle_larfg_d(m, &alpha, v + 1, &tau);
+        v[0] = 1.0;
+        B[c + c * ld] = alpha;
+        for (int64_t i = 1; i < m; ++i) B[c + i + c * ld] = 0.0;
+        left_d(B, ld, c, m, c + 1, n - 1, v, tau);
+        left_d(A, ld, c, m, 0, n - 1, v, tau);
+        fl += 4.0 * m * (double)(n - c - 1) + 4.0 * m * n;
+        if (Q) { right_d(Q, ld, c, m, 0, n - 1, v, tau); fl += 4.0 * m * n; }
+    }
+    for (int64_t j = 1; j <= n - 2; j += nb) {
+        const int64_t j2 = j + nb - 1 < n ? j + nb - 1 : n;
+        const int64_t num = n - nb - j + 1;
+        if (num <= 0) break;
+        const int64_t nblk = (num + (p - 1) * nb - 1) / ((p - 1) * nb);
+        /* left: QR of the blocks of the panel, from the bottom */
+        for (int64_t k = nblk - 1; k >= 0; --k) {
+            const int64_t i1 = j + nb + k * (p - 1) * nb;
+            const int64_t i2 = i1 + p * nb - 1 < n ? i1 + p * nb - 1 : n;
+            const int64_t rows = i2 - i1 + 1, cols = j2 - j + 1;
+            for (int64_t s = 0; s < rows && s < cols; ++s) {
+                const int64_t a = i1 - 1 + s, c = j - 1 + s, m = rows - s;
+                double alpha = A[a + c * ld], tau;
+                for (int64_t i = 1; i < m; ++i) v[i] = A[a + i + c * ld];
+                oracle_larfg_d(m, &alpha, v + 1, &tau);
+                v[0] = 1.0;
+                A[a + c * ld] = alpha;
+                for (int64_t i = 1; i < m; ++i) A[a + i + c * ld] = 0.0;
+                left_d(A, ld, a, m, c + 1, n - 1, v, tau);
+                left_d(B, ld, a, m, i1 - 1, n - 1, v, tau);
+                fl += 4.0 * m * (double)(n - c - 1) + 4.0 * m * (double)(n - i1 + 1);
+                if (Q) { right_d(Q, ld, a, m, 0, n - 1, v, tau); fl += 4.0 * m * n; }
+            }
+        }
+        /* right: RQ + LQ per block, from the bottom */
+        for (int64_t k = nblk - 1; k >= 0; --k) {
+            const int64_t i1 = j + nb + k * (p - 1) * nb;
+            const int64_t i2 = i1 + p * nb - 1 < n ? i1 + p * nb - 1 : n;
+            const int64_t m = i2 - i1 + 1, nr = nb < m ? nb : m, a = i1 - 1;
+            for (int64_t c = 0; c < m; ++c)
+                for (int64_t i = 0; i < m; ++i) W[i + c * m] = B[a + i + (a + c) * ld];
+            rq_accum_d(m, W, Y, u);
+            fl += 4.0 / 3.0 * (double)m * m * m + 2.0 * (double)m * m * m;
+            for (int64_t t = 0; t < nr; ++t)                  /* M = Qt(0:nr,:) = Y(:,0:nr)^H */
+                for (int64_t c = 0; c < m; ++c) M[t + c * nr] = Y[c + t * m];
+            for (int64_t t = 0; t < nr; ++t) {
+                const int64_t len = m - t;
+                double alpha = M[t + t * nr], tau;
+                for (int64_t c = 1; c < len; ++c) v[c] = M[t + (t + c) * nr];
+                oracle_larfg_d(len, &alpha, v + 1, &tau);
+                v[0] = 1.0;
+                M[t + t * nr] = alpha;
+                for (int64_t c = 1; c < len; ++c) M[t + (t + c) * nr] = 0.0;
+                if (tau == 0.0) continue;
+                for (int64_t rr = t + 1; rr < nr; ++rr) {      /* M(rr, t:m) <- M P_t */
+                    double s = 0.0;
+                    for (int64_t c = 0; c < len; ++c) s += M[rr + (t + c) * nr] * v[c];
+                    s *= tau;
+                    for (int64_t c = 0; c < len; ++c) M[rr + (t + c) * nr] -= s * v[c];
+                }
+                right_d(A, ld, a + t, len, 0, n - 1, v, tau);
+                right_d(B, ld, a + t, len, 0, i2 - 1, v, tau);
+                fl += 4.0 * len * (double)n + 4.0 * len * (double)i2;
+                if (Z) { right_d(Z, ld, a + t, len, 0, n - 1, v, tau); fl += 4.0 * len * n; }
+            }
+            for (int64_t c = 0; c < nr; ++c)
+                for (int64_t i = c + 1; i < m; ++i) B[a + i + (a + c) * ld] = 0.0;
+        }
+    }
+    /* exact zeros of the output contract: A r-Hessenberg, B upper triangular */
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = c + nb + 1; i < n; ++i) A[i + c * ld] = 0.0;
+        for (int64_t i = c + 1; i < n; ++i) B[i + c * ld] = 0.0;
+    }
+    if (flops) *flops += fl;
+    free(v); free(W); free(Y); free(M); free(u);
+    return 0;
+}
+
+int oracle_rhess_z(int64_t n, int64_t r, int64_t p, zdbl *A, zdbl *B, zdbl *Q, zdbl *Z,
+                   int64_t ld, double *flops)
+{
+    if (n < 0) return -1;
+    if (r < 1) return -2;
+    if (p < 2) return -3;
+    if (ld < (n > 1 ? n : 1)) return -8;
+    if (n == 0) return 0;
+    const int64_t nb = r < n - 1 ? r : (n > 1 ? n - 1 : 1);
+    const int64_t mb = p * nb;
+    zdbl *v = (zdbl *)malloc(sizeof(zdbl) * (size_t)(n + 1));
+    zdbl *W = (zdbl *)malloc(sizeof(zdbl) * (size_t)(mb * mb));
+    zdbl *Y = (zdbl *)malloc(sizeof(zdbl) * (size_t)(mb * mb));
+    zdbl *M = (zdbl *)malloc(sizeof(zdbl) * (size_t)(nb * mb));
+    zdbl *u = (zdbl *)malloc(sizeof(zdbl) * (size_t)(mb + 1));
+    if (!v || !W || !Y || !M || !u) { free(v); free(W); free(Y); free(M); free(u); return 1; }
+    double fl = 0.0;
+    for (int64_t c = 0; c + 1 < n; ++c) {
+        const int64_t m = n - c;
+        zdbl alpha = B[c + c * ld], tau;
+        for (int64_t i = 1; i < m; ++i) v[i] = B[c + i + c * ld];
+        oracle_larfg_z(m, &alpha, v + 1, &tau);
+        v[0] = zmk(1.0, 0.0);
+        B[c + c * ld] = alpha;
+        for (int64_t i = 1; i < m; ++i) B[c + i + c * ld] = zmk(0.0, 0.0);
+        left_z(B, ld, c, m, c + 1, n - 1, v, tau);
+        left_z(A, ld, c, m, 0, n - 1, v, tau);
+        fl += 4.0 * (4.0 * m * (double)(n - c - 1) + 4.0 * m * n);
+        if (Q) { right_z(Q, ld, c, m, 0, n - 1, v, tau); fl += 16.0 * m * n; }
+    }
+    for (int64_t j = 1; j <= n - 2; j += nb) {
+        const int64_t j2 = j + nb - 1 < n ? j + nb - 1 : n;
+        const int64_t num = n - nb - j + 1;
+        if (num <= 0) break;
+        const int64_t nblk = (num + (p - 1) * nb - 1) / ((p - 1) * nb);
+        for (int64_t k = nblk - 1; k >= 0; --k) {
+            const int64_t i1 = j + nb + k * (p - 1) * nb;
+            const int64_t i2 = i1 + p * nb - 1 < n ? i1 + p * nb - 1 : n;
+            const int64_t rows = i2 - i1 + 1, cols = j2 - j + 1;
+            for (int64_t s = 0; s < rows && s < cols; ++s) {
+                const int64_t a = i1 - 1 + s, c = j - 1 + s, m = rows - s;
+                zdbl alpha = A[a + c * ld], tau;
+                for (int64_t i = 1; i < m; ++i) v[i] = A[a + i + c * ld];
+                oracle_larfg_z(m, &alpha, v + 1, &tau);
+                v[0] = zmk(1.0, 0.0);
+                A[a + c * ld] = alpha;
+                for (int64_t i = 1; i < m; ++i) A[a + i + c * ld] = zmk(0.0, 0.0);
+                left_z(A, ld, a, m, c + 1, n - 1, v, tau);
+                left_z(B, ld, a, m, i1 - 1, n - 1, v, tau);
+                fl += 4.0 * (4.0 * m * (double)(n - c - 1) + 4.0 * m * (double)(n - i1 + 1));
+                if (Q) { right_z(Q, ld, a, m, 0, n - 1, v, tau); fl += 16.0 * m * n; }
+            }
+        }
+        for (int64_t k = nblk - 1; k >= 0; --k) {
+            const int64_t i1 = j + nb + k * (p - 1) * nb;
+            const int64_t i2 = i1 + p * nb - 1 < n ? i1 + p * nb - 1 : n;
+            const int64_t m = i2 - i1 + 1, nr = nb < m ? nb : m, a = i1 - 1;
+            for (int64_t c = 0; c < m; ++c)
+                for (int64_t i = 0; i < m; ++i) W[i + c * m] = B[a + i + (a + c) * ld];
+            rq_accum_z(m, W, Y, u);
+            fl += 4.0 * (4.0 / 3.0 * (double)m * m * m + 2.0 * (double)m * m * m);
+            for (int64_t t = 0; t < nr; ++t)                  /* M = Qt(0:nr,:) = Y(:,0:nr)^H */
+                for (int64_t c = 0; c < m; ++c) M[t + c * nr] = zconj(Y[c + t * m]);
+            for (int64_t t = 0; t < nr; ++t) {
+                const int64_t len = m - t;
+                /* reflector from conj(row t): (row t) P_t = beta e_0^T */
+                zdbl alpha = zconj(M[t + t * nr]), tau;
+                for (int64_t c = 1; c < len; ++c) v[c] = zconj(M[t + (t + c) * nr]);
+                oracle_larfg_z(len, &alpha, v + 1, &tau);
+                v[0] = zmk(1.0, 0.0);
+                M[t + t * nr] = alpha;
+                for (int64_t c = 1; c < len; ++c) M[t + (t + c) * nr] = zmk(0.0, 0.0);
+                if (tau.re == 0.0 && tau.im == 0.0) continue;
+                for (int64_t rr = t + 1; rr < nr; ++rr) {      /* M(rr, t:m) <- M P_t */
+                    zdbl s = zmk(0.0, 0.0);
+                    for (int64_t c = 0; c < len; ++c) s = zadd(s, zmul(M[rr + (t + c) * nr], v[c]));
+                    s = zmul(s, tau);
+                    for (int64_t c = 0; c < len; ++c) M[rr + (t + c) * nr] = zsub(M[rr + (t + c) * nr], zmul(s, zconj(v[c])));
+                }
+                right_z(A, ld, a + t, len, 0, n - 1, v, tau);
+                right_z(B, ld, a + t, len, 0, i2 - 1, v, tau);
+                fl += 4.0 * (4.0 * len * (double)n + 4.0 * len * (double)i2);
+                if (Z) { right_z(Z, ld, a + t, len, 0, n - 1, v, tau); fl += 16.0 * len * n; }
+            }
+            for (int64_t c = 0; c < nr; ++c)
+                for (int64_t i = c + 1; i < m; ++i) B[a + i + (a + c) * ld] = zmk(0.0, 0.0);
+        }
+    }
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = c + nb + 1; i < n; ++i) A[i + c * ld] = zmk(0.0, 0.0);
+        for (int64_t i = c + 1; i < n; ++i) B[i + c * ld] = zmk(0.0, 0.0);
+    }
+    if (flops) *flops += fl;
+    free(v); free(W); free(Y); free(M); free(u);
+    return 0;
+}

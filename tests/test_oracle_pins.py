@@ -282,3 +282,104 @@ def test_partial_sweeps_prefix():
     part = O.stage2(Hin, Tin, r, jmax=7)
     assert part[4] < full[4]
     assert np.all(np.tril(part[0][:, :7], -2) == 0)
+
+
+# ----------------------------------------------------------------- stage one
+# Stage one's intermediate r-HT output depends on the blocking (nb, p); what
+# the problem fixes is checked: the structure, orthogonality, backward error,
+# the first columns of Q and Z, and (after stage two) the canonical HT form.
+
+def _rhess_check(A, B, r, p):
+    n = A.shape[0]
+    Ao, Bo, Q, Z, fl = O.rhess(A, B, r, p)
+    rr = min(r, max(n - 1, 1))
+    assert np.all(np.tril(Ao, -(rr + 1)) == 0) and np.all(np.tril(Bo, -1) == 0)
+    I = np.eye(n)
+    bound = 100 * max(n, 1) * EPS
+    assert fro(Q.conj().T @ Q - I) <= bound and fro(Z.conj().T @ Z - I) <= bound
+    assert fro(Q @ Ao @ Z.conj().T - A) / fro(A) <= bound
+    assert fro(Q @ Bo @ Z.conj().T - B) / fro(B) <= bound
+    return Ao, Bo, Q, Z
+
+
+@pytest.mark.parametrize("n,r,p,cplx", [(30, 4, 3, False), (64, 8, 8, False), (100, 16, 4, False), (37, 5, 2, False),
+                                        (50, 6, 3, True), (12, 3, 8, True), (8, 7, 2, False), (40, 39, 2, False),
+                                        (3, 1, 2, False), (1, 2, 2, False)])
+def test_rhess_invariants(n, r, p, cplx):
+    """P1-P3 for stage one: r-Hessenberg A and triangular B with exact zeros,
+    orthogonal Q and Z, backward error within 100 n eps."""
+    A, B = inputs.dense_pencil(n, seed=n + 7 * r + p, complex_=cplx)
+    _rhess_check(A, B, r, p)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_rhess_first_columns(cplx):
+    """Stage one's reflectors act on rows and columns >= j + nb >= 2, so Z e1 = e1
+    bitwise, and Q e1 is the first column of the QR factor of B: B e1 / R11."""
+    n, r, p = 45, 5, 3
+    A, B = inputs.dense_pencil(n, seed=3, complex_=cplx)
+    Ao, Bo, Q, Z = _rhess_check(A, B, r, p)
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    assert np.array_equal(Z[:, 0], e1)
+    assert fro(Q[:, 0] - B[:, 0] / Bo[0, 0]) <= 100 * n * EPS
+
+
+@pytest.mark.parametrize("n,r,p,cplx", [(40, 4, 3, False), (72, 8, 4, False), (60, 6, 8, False), (36, 4, 3, True)])
+def test_full_path_canonical_form_matches_gghrd(n, r, p, cplx):
+    """P11: stage one then stage two equals LAPACK xGGHRD applied to
+    (Q_B^H A, R_B) (Q_B from an independent QR of B) once the diagonal
+    unimodular freedom is normalised; both fix the first column of Q to Q_B e1."""
+    A, B = inputs.dense_pencil(n, seed=11 + n, complex_=cplx)
+    A1, B1, Q1, Z1, _ = O.rhess(A, B, r, p)
+    H, T, Q, Z, _ = O.stage2(A1, B1, r, Q=Q1, Z=Z1)
+    QB, RB = np.linalg.qr(B)
+    ref = LR.gghrd(QB.conj().T @ A, np.triu(RB))
+    if ref is None:
+        pytest.skip("xGGHRD not exported by the bundled LAPACK")
+    Hg, Tg, Qg, Zg = ref
+    a = LR.canonical(H, T, Q, Z)
+    b = LR.canonical(Hg, Tg, QB @ Qg, Zg)
+    for x, y in zip(a, b):
+        assert fro(x - y) / max(fro(y), 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (7, 1), (8, 2)])
+def test_rhess_eigenvalues_brute_force_tiny(n, seed):
+    """Generalized eigenvalues survive stage one: roots of det(A - lam B) in exact arithmetic."""
+    A, B = inputs.dense_pencil(n, seed=seed)
+    poly = LR.charpoly_exact(A, B)
+    roots = np.roots([float(c) for c in reversed(poly)])
+    Ao, Bo, Q, Z, _ = O.rhess(A, B, 2, 2)
+    ev = sla.eigvals(Ao, Bo)
+    C = np.abs(roots[:, None] - ev[None, :])
+    i, j = linear_sum_assignment(C)
+    assert np.all(C[i, j] <= 1e-7 * (1 + np.abs(roots[i])))
+
+
+def test_rhess_complex_on_real_input_equals_real():
+    n, r, p = 33, 4, 3
+    A, B = inputs.dense_pencil(n, seed=5)
+    re_ = O.rhess(A, B, r, p)
+    ce = O.rhess(A.astype(np.complex128), B.astype(np.complex128), r, p)
+    for x, y in zip(re_[:4], ce[:4]):
+        assert fro(x - y) <= 1e-12 * max(fro(x), 1.0)
+
+
+def test_two_stage_singular_b_saddle_point():
+    """Saddle-point pencil ([X Y; Y^T 0], [I 0; 0 0]) with a quarter of infinite
+    eigenvalues: B and its diagonal blocks are singular, which the RQ-based
+    opposite reflectors must handle (both stages)."""
+    n, r, p = 48, 4, 3
+    A, B = inputs.saddle_point_pencil(n, 0.25, seed=2)
+    A1, B1, Q1, Z1 = _rhess_check(A, B, r, p)
+    H, T, Q, Z, _ = O.stage2(A1, B1, r, Q=Q1, Z=Z1)
+    assert np.all(np.tril(H, -2) == 0) and np.all(np.tril(T, -1) == 0)
+    bound = 100 * n * EPS
+    assert fro(Q @ H @ Z.T - A) / fro(A) <= bound and fro(Q @ T @ Z.T - B) / fro(B) <= bound
+    # equivalence keeps the rank of B; a triangular T of that rank has at least
+    # n - rank(B) (numerically) zero diagonal entries
+    rk = np.linalg.matrix_rank(B)
+    assert rk == n - n // 4 and np.linalg.matrix_rank(T) == rk
+    d = np.abs(np.diag(T))
+    assert np.sum(d < 1e-10 * np.abs(T).max()) >= n - rk

@@ -111,17 +111,31 @@ int ht_stage2_batched_z(int64_t count, void *const *H, void *const *T,
 /*
  * ht_rhess -- stage one: reduce a dense pencil (A, B) to r-Hessenberg-
  * triangular form (Section 2.2, blocked stage-one algorithm in the appendix),
- * after a Householder QR factorisation of B (Section 4).  Panel width n_b = r,
- * p = 8 panel blocks per QR.
- *   A, B (in/out): on exit A is r-Hessenberg (exact zeros below) and B upper
- *   triangular (exact zeros below); Q <- Q*Q1, Z <- Z*Z1 with
- *   (A_in, B_in) = Q1 (A_out, B_out) Z1^H; Q, Z may be NULL.
- * Errors as ht_stage2.
+ * after a QR factorisation of B (the experiments of Section 4 replace B by
+ * the R factor of its QR).  Panel width n_b = min(r, n-1) <= 32; the blocks
+ * of the panel QRs have p*n_b rows (p panel blocks, overlapping by n_b),
+ * p = ht_rhess_default_p(n, r) (the largest p <= 8 with p*n_b <= 64, at
+ * least 2); ht_rhess_p takes p explicitly (2 <= p, p*n_b <= 64, else -8).
+ *   A, B (in/out): dense on entry; on exit A is r-Hessenberg (exact zeros
+ *   below the r-th subdiagonal) and B upper triangular (exact zeros below);
+ *   Q <- Q*Q1, Z <- Z*Z1 with (A_in, B_in) = Q1 (A_out, B_out) Z1^H, where
+ *   Q1 e1 is the first column of the QR factor of B and Z1 e1 = e1.  Q, Z
+ *   may be NULL.  The output depends on (n_b, p); the HT form reached after
+ *   ht_stage2 does not (up to the unimodular diagonal scaling that the
+ *   reflector conventions fix).
+ * Errors as ht_stage2 (-5 n, -6 r, -7 ld, -1/-2 NULL A/B, -8 p);
+ * HT_ERR_NOTSUP for n_b > 32.
  */
 int ht_rhess(double *A, double *B, double *Q, double *Z,
              int64_t n, int64_t r, int64_t ld, void *stream);
 int ht_rhess_z(void *A, void *B, void *Q, void *Z,
                int64_t n, int64_t r, int64_t ld, void *stream);
+int ht_rhess_p(double *A, double *B, double *Q, double *Z,
+               int64_t n, int64_t r, int64_t ld, int64_t p, void *stream);
+int ht_rhess_z_p(void *A, void *B, void *Q, void *Z,
+                 int64_t n, int64_t r, int64_t ld, int64_t p, void *stream);
+/* The built-in p of ht_rhess for (n, r); -1 for n < 0 or r < 1. */
+int64_t ht_rhess_default_p(int64_t n, int64_t r);
 
 /*
  * Device workspace (bytes) that a call with these sizes takes from the

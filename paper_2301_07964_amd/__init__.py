@@ -45,6 +45,11 @@ def lib(with_torch: bool = True):
         getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp]
     for f in ("ht_stage2", "ht_stage2_z", "ht_rhess", "ht_rhess_z"):
         getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp]
+    for f in ("ht_rhess_p", "ht_rhess_z_p"):
+        getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp]
+        getattr(L, f).restype = _int
+    L.ht_rhess_default_p.argtypes = [_i64, _i64]
+    L.ht_rhess_default_p.restype = _i64
     for f in ("ht_stage2_q", "ht_stage2_z_q", "ht_stage2", "ht_stage2_z", "ht_rhess", "ht_rhess_z",
               "ht_stage2_batched", "ht_stage2_batched_z"):
         getattr(L, f).restype = _int
@@ -69,7 +74,8 @@ def lib(with_torch: bool = True):
 
 EXPORTS = (
     "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_batched",
-    "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_workspace_bytes",
+    "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_rhess_p", "ht_rhess_z_p", "ht_rhess_default_p",
+    "ht_workspace_bytes",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
     "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms",
 )
@@ -169,21 +175,29 @@ def stage2(H, T, r: int, Q=None, Z=None, q: int = 0, stream=None):
     return H, T, Q, Z
 
 
-def rhess(A, B, r: int, Q=None, Z=None, stream=None):
-    """Stage one: reduce the dense pencil (A, B) in place to r-HT form."""
+def rhess(A, B, r: int, Q=None, Z=None, p: int = 0, stream=None):
+    """Stage one: reduce the dense pencil (A, B) in place to r-HT form.
+
+    Q, Z (optional) are updated in place: Q <- Q Q1, Z <- Z Z1.  p = 0 takes
+    the library's choice of panel blocks (``rhess_default_p``).
+    """
     n = A.shape[0]
     cplx = A.is_complex()
     ptrs, lds = [], []
     for t, nm in ((A, "A"), (B, "B"), (Q, "Q"), (Z, "Z")):
-        p, ld = _layout(t, n, nm, cplx)
-        ptrs.append(p)
+        pt, ld = _layout(t, n, nm, cplx)
+        ptrs.append(pt)
         if ld is not None:
             lds.append(ld)
     if len(set(lds)) != 1:
         raise ValueError("A, B, Q, Z must share the leading dimension")
-    f = lib().ht_rhess_z if cplx else lib().ht_rhess
-    _check(f(*ptrs, n, r, lds[0], _stream_ptr(stream)), "ht_rhess")
+    f = lib().ht_rhess_z_p if cplx else lib().ht_rhess_p
+    _check(f(*ptrs, n, r, lds[0], p, _stream_ptr(stream)), "ht_rhess")
     return A, B, Q, Z
+
+
+def rhess_default_p(n: int, r: int) -> int:
+    return int(lib().ht_rhess_default_p(n, r))
 
 
 def stage2_batched(pencils, q=None, stream=None):

@@ -4,6 +4,4 @@
 #include <stdint.h>
 
 extern "C" {
-int ht_rhess(double *, double *, double *, double *, int64_t, int64_t, int64_t, void *) { return HT_ERR_NOTSUP; }
-int ht_rhess_z(void *, void *, void *, void *, int64_t, int64_t, int64_t, void *) { return HT_ERR_NOTSUP; }
 }

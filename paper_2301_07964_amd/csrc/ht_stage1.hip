@@ -81,9 +81,19 @@ __global__ __launch_bounds__(256) void k_s1_block_qr(S *X, int64_t ld, Blocks bl
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t r0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - r0 + 1);
-        for (int e = tid; e < m * nc; e += 256) {
-            const int i = e % m, s = e / m;
-            P[s * bm + i] = X[r0 + i + (c0 + s) * ld];
+        {
+            constexpr int NT = kS1MaxBM * kS1MaxNB / 256;      // fixed trip count: loads in flight together
+            S buf[NT];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int e = tid + 256 * u, i = e % m, s = e / m;
+                buf[u] = e < m * nc ? X[r0 + i + (c0 + s) * ld] : zero<S>();
+            }
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int e = tid + 256 * u, i = e % m, s = e / m;
+                if (e < m * nc) P[s * bm + i] = buf[u];
+            }
         }
         __syncthreads();
         const int ns = m < nc ? m : nc;
@@ -138,51 +148,86 @@ __global__ __launch_bounds__(256) void k_s1_block_qr(S *X, int64_t ld, Blocks bl
     }
 }
 
+// Stage block k's reflectors (m x nc, column s at s*bm) and taus into LDS;
+// 64 threads, fixed trip counts so that the loads are in flight together.
+template <class S>
+__device__ inline void stage_refl(S *vs, S *ts, const S *V, const S *tau, int64_t k, int bm, int nc, int t)
+{
+    const S *Vk = V + k * bm * nc;
+    constexpr int CH = 16;
+    const int tot = bm * nc;
+    for (int e0 = 0; e0 < tot; e0 += 64 * CH) {
+        S buf[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = e0 + u * 64 + t;
+            buf[u] = e < tot ? Vk[e] : zero<S>();
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = e0 + u * 64 + t;
+            if (e < tot) vs[e] = buf[u];
+        }
+    }
+    if (t < nc) ts[t] = tau[k * nc + t];
+}
+
 // ------------------------------------------------------ left chain (columns)
 // For k = nblk-1 .. 0: X(block k rows, c) <- Q_k^H X(block k rows, c) for the
 // columns c in [cfirst, clast] with c >= (cfrom_block ? r0(k) : cfirst).
-// 64 columns per workgroup, the block rows of each column staged in LDS.
+// 64 columns per workgroup; the block rows of the columns and the block's
+// reflectors are staged in LDS.
 template <class S>
 __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
                                                       int64_t cfirst, int64_t clast, int cfrom_block)
 {
     __shared__ S xs[kS1MaxBM * 65];
+    __shared__ S vs[kS1MaxBM * kS1MaxNB];
+    __shared__ S ts[kS1MaxNB];
     const int t = threadIdx.x;
     const int64_t cb = cfirst + (int64_t)blockIdx.x * 64;
     const int64_t c = cb + t;
     const int bm = (int)bl.bm;
+    constexpr int CH = 16;
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t r0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - r0 + 1);
         const int64_t clo = cfrom_block ? i64max(cfirst, r0) : cfirst;
         if (cb + 63 < clo) continue;                        // uniform: the workgroup has no column here
-        for (int cc = 0; cc < 64; ++cc) {
-            const int64_t col = cb + cc;
-            if (col > clast) break;
-            for (int i = t; i < m; i += 64) xs[i * 65 + cc] = X[r0 + i + col * ld];
+        stage_refl(vs, ts, V, tau, k, bm, nc, t);
+        // tile: thread t loads row t of the block for 64 columns (coalesced along rows)
+        for (int c0 = 0; c0 < 64; c0 += CH) {
+            S buf[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int64_t col = cb + c0 + u;
+                buf[u] = (t < m && col <= clast) ? X[r0 + t + col * ld] : zero<S>();
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) xs[t * 65 + c0 + u] = buf[u];
         }
         __syncthreads();
         if (c <= clast && c >= clo) {
             const int ns = m < nc ? m : nc;
-            const S *Vk = V + k * bm * nc;
             for (int s = 0; s < ns; ++s) {
-                const S ts = tau[k * nc + s];
-                if (iszero(ts)) continue;
-                const S *v = Vk + s * bm;
+                const S tsv = ts[s];
+                if (iszero(tsv)) continue;
+                const S *v = vs + s * bm;
                 S d0 = zero<S>(), d1 = zero<S>();
                 int i = s;
                 for (; i + 1 < m; i += 2) { d0 = add(d0, cmul(v[i], xs[i * 65 + t])); d1 = add(d1, cmul(v[i + 1], xs[(i + 1) * 65 + t])); }
                 if (i < m) d0 = add(d0, cmul(v[i], xs[i * 65 + t]));
-                const S d = mul(conj_(ts), add(d0, d1));
+                const S d = mul(conj_(tsv), add(d0, d1));
                 for (int ii = s; ii < m; ++ii) xs[ii * 65 + t] = sub(xs[ii * 65 + t], mul(d, v[ii]));
             }
         }
         __syncthreads();
-        for (int cc = 0; cc < 64; ++cc) {
-            const int64_t col = cb + cc;
-            if (col > clast) break;
-            if (col < clo) continue;
-            for (int i = t; i < m; i += 64) X[r0 + i + col * ld] = xs[i * 65 + cc];
+        for (int c0 = 0; c0 < 64; c0 += CH) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int64_t col = cb + c0 + u;
+                if (t < m && col <= clast && col >= clo) X[r0 + t + col * ld] = xs[t * 65 + c0 + u];
+            }
         }
         __syncthreads();
     }
@@ -191,36 +236,51 @@ __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks b
 // ------------------------------------------------------ right chain (rows)
 // For k = nblk-1 .. 0: X(rho, block k columns) <- X(rho, block k columns) G_0
 // ... G_{nc-1} for rows rho in [0, rlast]; the block's columns are the block's
-// rows (r0(k) .. r1(k)).  64 rows per workgroup.
+// rows (r0(k) .. r1(k)).  64 rows per workgroup, reflectors staged in LDS.
 template <class S>
 __global__ __launch_bounds__(64) void k_s1_right_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
                                                        int64_t rlast)
 {
     __shared__ S xs[64 * (kS1MaxBM + 1)];
+    __shared__ S vs[kS1MaxBM * kS1MaxNB];
+    __shared__ S ts[kS1MaxNB];
     const int t = threadIdx.x;
     const int64_t rho = (int64_t)blockIdx.x * 64 + t;
     const bool ok = rho <= rlast;
     const int bm = (int)bl.bm;
+    constexpr int CH = 16;
     S *x = xs + t * (kS1MaxBM + 1);
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t c0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - c0 + 1);
-        if (!ok) continue;
-        for (int cc = 0; cc < m; ++cc) x[cc] = X[rho + (c0 + cc) * ld];
-        const int ns = m < nc ? m : nc;
-        const S *Vk = V + k * bm * nc;
-        for (int s = 0; s < ns; ++s) {
-            const S ts = tau[k * nc + s];
-            if (iszero(ts)) continue;
-            const S *v = Vk + s * bm;
-            S d0 = zero<S>(), d1 = zero<S>();
-            int i = s;
-            for (; i + 1 < m; i += 2) { d0 = add(d0, mul(x[i], v[i])); d1 = add(d1, mul(x[i + 1], v[i + 1])); }
-            if (i < m) d0 = add(d0, mul(x[i], v[i]));
-            const S d = mul(add(d0, d1), ts);
-            for (int ii = s; ii < m; ++ii) x[ii] = sub(x[ii], mul(d, conj_(v[ii])));
+        __syncthreads();
+        stage_refl(vs, ts, V, tau, k, bm, nc, t);
+        for (int cc0 = 0; cc0 < kS1MaxBM; cc0 += CH) {
+            S buf[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int cc = cc0 + u;
+                buf[u] = (ok && cc < m) ? X[rho + (c0 + cc) * ld] : zero<S>();
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) x[cc0 + u] = buf[u];
         }
-        for (int cc = 0; cc < m; ++cc) X[rho + (c0 + cc) * ld] = x[cc];
+        __syncthreads();
+        if (ok) {
+            const int ns = m < nc ? m : nc;
+            for (int s = 0; s < ns; ++s) {
+                const S tsv = ts[s];
+                if (iszero(tsv)) continue;
+                const S *v = vs + s * bm;
+                S d0 = zero<S>(), d1 = zero<S>();
+                int i = s;
+                for (; i + 1 < m; i += 2) { d0 = add(d0, mul(x[i], v[i])); d1 = add(d1, mul(x[i + 1], v[i + 1])); }
+                if (i < m) d0 = add(d0, mul(x[i], v[i]));
+                const S d = mul(add(d0, d1), tsv);
+                for (int ii = s; ii < m; ++ii) x[ii] = sub(x[ii], mul(d, conj_(v[ii])));
+            }
+            for (int cc = 0; cc < m; ++cc) X[rho + (c0 + cc) * ld] = x[cc];
+        }
     }
 }
 
@@ -246,9 +306,19 @@ __global__ __launch_bounds__(256) void k_s1_right_factor(const S *B, int64_t ld,
     const int64_t r0 = bl.r0(k);
     const int m = (int)(bl.r1(k) - r0 + 1);
     const int nr = m < nb ? m : nb;
-    for (int e = tid; e < m * m; e += 256) {
-        const int i = e % m, c = e / m;
-        W[i * LW + c] = B[r0 + i + (r0 + c) * ld];
+    {
+        constexpr int NT = kS1MaxBM * kS1MaxBM / 256;      // fixed trip count: loads in flight together
+        S buf[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int e = tid + 256 * u, i = e % m, c = e / m;
+            buf[u] = e < m * m ? B[r0 + i + (r0 + c) * ld] : zero<S>();
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int e = tid + 256 * u, i = e % m, c = e / m;
+            if (e < m * m) W[i * LW + c] = buf[u];
+        }
     }
     __syncthreads();
     // RQ, rows m-1 .. 1: u = conj(row i)(0..i), larfg with alpha = u_i

@@ -203,16 +203,20 @@ def bench_serving(args):
     same run; both policies replay the same trace.  Reports p50/p99 latency
     (completion - arrival, host clock, queueing included) and pencils/s."""
     import numpy as np
+    # one hardware queue per execution stream (6 slots x 2 streams + the batch
+    # stream); HIP reads this when it initialises, below
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
     import torch
     import paper_2301_07964_amd.serving as S
 
     torch.cuda.set_device(0)
-    count = args.count if args.count != 2048 else 60
+    count = args.count if args.count != 2048 else 40
     # calibration: FIFO service of a sample that arrives at once
     cal = S.make_trace(12, rate=0.0, seed=args.seed + 1)
     print(f"[bench] calibration: {len(cal)} requests, n={[q.n for q in cal]}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    S.Engine("fifo").run(cal, time_limit=1200)
+    S.Engine("fifo").run(cal, time_limit=1200, progress=lambda k, tot, now: print(
+        f"[bench] calibration: {k}/{tot} done at {now:.1f} s", file=sys.stderr, flush=True))
     t_cal = time.perf_counter() - t0
     cap = len(cal) / t_cal
     lam = 0.8 * cap
@@ -222,7 +226,10 @@ def bench_serving(args):
         trace = S.make_trace(count, rate=lam, seed=args.seed)
         eng = S.Engine(policy)
         t0 = time.perf_counter()
-        eng.run(trace, time_limit=1500)
+
+        def progress(k, tot, now, policy=policy):
+            print(f"[bench] {policy}: {k}/{tot} requests done at {now:.1f} s", file=sys.stderr, flush=True)
+        eng.run(trace, time_limit=1500, progress=progress)
         wall = time.perf_counter() - t0
         res[policy] = dict(S.summary(trace), wall_s=round(wall, 3), max_inflight=eng.max_inflight,
                            peak_accounted_gb=round(eng.peak_bytes / 2 ** 30, 2))

@@ -144,6 +144,23 @@ int64_t ht_rhess_default_p(int64_t n, int64_t r);
  */
 int64_t ht_workspace_bytes(int64_t n, int64_t r, int64_t q, int is_complex);
 
+/*
+ * Device workspace (bytes) that ht_rhess / ht_rhess_p takes from the
+ * per-stream cache (p = 0: built-in choice).  Returns -1 for invalid sizes
+ * (including r > 32 or p out of range).
+ */
+int64_t ht_rhess_workspace_bytes(int64_t n, int64_t r, int64_t p, int is_complex);
+
+/*
+ * Grow the workspace cached for (current device, stream) to at least `bytes`
+ * now (blocking: an existing smaller buffer is released after the stream has
+ * drained).  Later calls on that stream whose workspace fits neither allocate
+ * nor synchronise, which keeps a request loop's host thread from stalling
+ * when a larger request arrives.  Returns 0, -1 for bytes < 0, or
+ * HT_ERR_NOMEM / HT_ERR_HIP.
+ */
+int ht_reserve_workspace(int64_t bytes, void *stream);
+
 /* Release the calling thread's cached workspaces on the current device. */
 void ht_release_workspace(void);
 

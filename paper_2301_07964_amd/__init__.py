@@ -57,6 +57,10 @@ def lib(with_torch: bool = True):
     L.ht_stage2_batched_z.argtypes = [_i64, _P, _P, _P, _P, _PI, _PI, _PI, _PI, _vp]
     L.ht_workspace_bytes.argtypes = [_i64, _i64, _i64, _int]
     L.ht_workspace_bytes.restype = _i64
+    L.ht_rhess_workspace_bytes.argtypes = [_i64, _i64, _i64, _int]
+    L.ht_rhess_workspace_bytes.restype = _i64
+    L.ht_reserve_workspace.argtypes = [_i64, _vp]
+    L.ht_reserve_workspace.restype = _int
     L.ht_default_q.argtypes = [_i64, _i64]
     L.ht_default_q.restype = _i64
     L.ht_strerror.argtypes = [_int]
@@ -75,7 +79,7 @@ def lib(with_torch: bool = True):
 EXPORTS = (
     "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_batched",
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_rhess_p", "ht_rhess_z_p", "ht_rhess_default_p",
-    "ht_workspace_bytes",
+    "ht_workspace_bytes", "ht_rhess_workspace_bytes", "ht_reserve_workspace",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
     "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms",
 )
@@ -116,6 +120,16 @@ def version() -> str:
 
 def workspace_bytes(n: int, r: int, q: int = 0, complex_: bool = False) -> int:
     return int(lib().ht_workspace_bytes(n, r, q, 1 if complex_ else 0))
+
+
+def rhess_workspace_bytes(n: int, r: int, p: int = 0, complex_: bool = False) -> int:
+    return int(lib().ht_rhess_workspace_bytes(n, r, p, 1 if complex_ else 0))
+
+
+def reserve_workspace(nbytes: int, stream=None):
+    """Pre-size the library workspace of ``stream`` (default: torch's current
+    stream) so that later calls on it never allocate."""
+    _check(lib().ht_reserve_workspace(int(nbytes), _stream_ptr(stream)), "ht_reserve_workspace")
 
 
 def default_q(n: int, r: int) -> int:

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <vector>
+#include <string.h>
+#include <stdio.h>
 
 namespace ht {
 
@@ -235,9 +237,14 @@ static int batched_impl(int64_t count, S *const *H, S *const *T, S *const *Q, S 
     int *counter = (int *)(ws + dal);              // work queue position
     unsigned long long *stamps = timed ? (unsigned long long *)(ws + dal + 256) : nullptr;
     g_stamps = BatchStamps{stamps, timed ? count : 0, st};
-    // the descriptors are copied before the call returns (pageable source)
-    if (hipMemcpyAsync(dp, hp.data(), dbytes, hipMemcpyHostToDevice, st) != hipSuccess) return HT_ERR_HIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return HT_ERR_HIP;
+    // the descriptors go through this stream's pinned staging buffer, so the
+    // call does not wait for the stream; the host arrays are read before return
+    PinnedEntry *pe = pinned_get(dbytes, st);
+    if (!pe) { snprintf(g_errmsg, sizeof(g_errmsg), "pinned staging buffer"); return HT_ERR_HIP; }
+    memcpy(pe->ptr, hp.data(), dbytes);
+    if (hipMemcpyAsync(dp, pe->ptr, dbytes, hipMemcpyHostToDevice, st) != hipSuccess) return HT_ERR_HIP;
+    if (hipEventRecord(pe->done, st) != hipSuccess) return HT_ERR_HIP;
+    pe->pending = true;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
     if ((rc = launch_check("k_reset_counter"))) return rc;
     int dev = 0, ncu = 256;

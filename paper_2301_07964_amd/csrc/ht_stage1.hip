@@ -70,79 +70,70 @@ struct Blocks {
 // QR of X(block k rows, cols c0..c0+nc-1) for k = nblk-1 .. 0 (one
 // workgroup).  The R factor and exact zeros go back to X; the reflectors to
 // V[k*bm*nc + s*bm + i] (unit lower trapezoidal, zeros above) and tau[k*nc+s].
+// Column s of the block is held in registers by the 8 threads 8s..8s+7
+// (rows 8u + (tid & 7)); one barrier per reflector.
 template <class S>
 __global__ __launch_bounds__(256) void k_s1_block_qr(S *X, int64_t ld, Blocks bl, int64_t c0, int nc, S *V, S *tau)
 {
-    __shared__ S P[kS1MaxBM * kS1MaxNB];
-    __shared__ double red[4];
-    __shared__ S sc[3];
-    const int tid = threadIdx.x;
+    __shared__ S vb[2][kS1MaxBM];
+    __shared__ S tb[2];
+    const int tid = threadIdx.x, s = tid >> 3, part = tid & 7;
     const int bm = (int)bl.bm;
+    const bool col = s < nc;
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t r0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - r0 + 1);
-        {
-            constexpr int NT = kS1MaxBM * kS1MaxNB / 256;      // fixed trip count: loads in flight together
-            S buf[NT];
+        S x[8];
 #pragma unroll
-            for (int u = 0; u < NT; ++u) {
-                const int e = tid + 256 * u, i = e % m, s = e / m;
-                buf[u] = e < m * nc ? X[r0 + i + (c0 + s) * ld] : zero<S>();
-            }
-#pragma unroll
-            for (int u = 0; u < NT; ++u) {
-                const int e = tid + 256 * u, i = e % m, s = e / m;
-                if (e < m * nc) P[s * bm + i] = buf[u];
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int i = 8 * u + part;
+            x[u] = (col && i < m) ? X[r0 + i + (c0 + s) * ld] : zero<S>();
         }
-        __syncthreads();
         const int ns = m < nc ? m : nc;
-        for (int s = 0; s < ns; ++s) {
-            double part = 0.0;
-            for (int i = s + 1 + tid; i < m; i += 256) part += abs2(P[s * bm + i]);
-            const double ss = block_sum256(part, red);
-            if (tid == 0) {
-                S t, b, f;
+        for (int st = 0; st < ns; ++st) {
+            const int b = st & 1;
+            if (s == st) {                                   // the pivot column's 8 threads
+                S al = zero<S>();
+                double ssp = 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = 8 * u + part;
+                    al = sel(i == st, x[u], al);
+                    ssp += (i > st) ? abs2(x[u]) : 0.0;     // rows >= m hold zeros
+                }
+                al = group_sum<8>(al);
+                const double ss = group_sum<8>(ssp);
+                S t, be, f;
                 bool triv;
-                larfg_scalars(P[s * bm + s], ss, t, b, f, triv);
-                sc[0] = t; sc[1] = b; sc[2] = f;
-            }
-            __syncthreads();
-            const S t = sc[0], f = sc[2];
-            for (int i = s + 1 + tid; i < m; i += 256) P[s * bm + i] = iszero(t) ? P[s * bm + i] : mul(P[s * bm + i], f);
-            if (tid == 0) P[s * bm + s] = sc[1];
-            for (int i = tid; i < bm; i += 256) {
-                S v = zero<S>();
-                if (i == s) v = one<S>();
-                else if (i > s && i < m) v = P[s * bm + i];
-                V[(k * bm + 0) * nc + s * bm + i] = v;
-            }
-            if (tid == 0) tau[k * nc + s] = t;
-            __syncthreads();
-            // apply G^H to the remaining columns of the block: 8 threads per column
-            if (!iszero(t)) {
-                const int c = s + 1 + (tid >> 3), sub8 = tid & 7;
-                S part2 = zero<S>();
-                if (c < nc) {
-                    for (int i = s + sub8; i < m; i += 8) {
-                        const S vi = (i == s) ? one<S>() : P[s * bm + i];
-                        part2 = add(part2, cmul(vi, P[c * bm + i]));
-                    }
+                larfg_scalars(al, ss, t, be, f, triv);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = 8 * u + part;
+                    S v = zero<S>();
+                    if (i == st) v = one<S>();
+                    else if (i > st && i < m) v = iszero(t) ? x[u] : mul(x[u], f);
+                    if (i < bm) V[(k * bm) * nc + st * bm + i] = v;
+                    vb[b][i] = v;
+                    x[u] = (i == st) ? be : ((i > st) ? zero<S>() : x[u]);
                 }
-                const S dot = mul(conj_(t), group_sum<8>(part2));
-                if (c < nc) {
-                    for (int i = s + sub8; i < m; i += 8) {
-                        const S vi = (i == s) ? one<S>() : P[s * bm + i];
-                        P[c * bm + i] = sub(P[c * bm + i], mul(dot, vi));
-                    }
-                }
+                if (part == 0) { tau[k * nc + st] = t; tb[b] = t; }
             }
             __syncthreads();
+            const S tt = tb[b];
+            if (s > st && col && !iszero(tt)) {              // G^H on the later columns
+                S p = zero<S>();
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p = add(p, cmul(vb[b][8 * u + part], x[u]));
+                const S d = mul(conj_(tt), group_sum<8>(p));
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = sub(x[u], mul(d, vb[b][8 * u + part]));
+            }
         }
-        // R and exact zeros back to X
-        for (int e = tid; e < m * nc; e += 256) {
-            const int i = e % m, s = e / m;
-            X[r0 + i + (c0 + s) * ld] = (i <= s) ? P[s * bm + i] : zero<S>();
+        // R and exact zeros back to X (the next block reads the overlap rows)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = 8 * u + part;
+            if (col && i < m) X[r0 + i + (c0 + s) * ld] = x[u];
         }
         __syncthreads();
     }
@@ -172,62 +163,70 @@ __device__ inline void stage_refl(S *vs, S *ts, const S *V, const S *tau, int64_
     if (t < nc) ts[t] = tau[k * nc + t];
 }
 
+constexpr int kS1Cols = 16;      // columns (left chain) or rows (right chain) per workgroup
+
 // ------------------------------------------------------ left chain (columns)
 // For k = nblk-1 .. 0: X(block k rows, c) <- Q_k^H X(block k rows, c) for the
 // columns c in [cfirst, clast] with c >= (cfrom_block ? r0(k) : cfirst).
-// 64 columns per workgroup; the block rows of the columns and the block's
-// reflectors are staged in LDS.
+// 16 columns per workgroup of 64 threads: the block's rows are staged through
+// LDS with coalesced loads, then column cc is held in registers by the four
+// threads 4cc..4cc+3 (rows 4u + (t & 3)).
 template <class S>
 __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
                                                       int64_t cfirst, int64_t clast, int cfrom_block)
 {
-    __shared__ S xs[kS1MaxBM * 65];
+    constexpr int CW = kS1Cols, LT = CW + 1;
+    __shared__ S xs[kS1MaxBM * LT];                 // row i, column cc at xs[i*LT + cc]
     __shared__ S vs[kS1MaxBM * kS1MaxNB];
     __shared__ S ts[kS1MaxNB];
-    const int t = threadIdx.x;
-    const int64_t cb = cfirst + (int64_t)blockIdx.x * 64;
-    const int64_t c = cb + t;
+    const int t = threadIdx.x, cc = t >> 2, part = t & 3;
+    const int64_t cb = cfirst + (int64_t)blockIdx.x * CW;
     const int bm = (int)bl.bm;
-    constexpr int CH = 16;
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t r0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - r0 + 1);
         const int64_t clo = cfrom_block ? i64max(cfirst, r0) : cfirst;
-        if (cb + 63 < clo) continue;                        // uniform: the workgroup has no column here
+        if (cb + CW - 1 < clo) continue;                // uniform: the workgroup has no column here
         stage_refl(vs, ts, V, tau, k, bm, nc, t);
-        // tile: thread t loads row t of the block for 64 columns (coalesced along rows)
-        for (int c0 = 0; c0 < 64; c0 += CH) {
-            S buf[CH];
+        {
+            S buf[CW];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int64_t col = cb + c0 + u;
+            for (int u = 0; u < CW; ++u) {
+                const int64_t col = cb + u;
                 buf[u] = (t < m && col <= clast) ? X[r0 + t + col * ld] : zero<S>();
             }
 #pragma unroll
-            for (int u = 0; u < CH; ++u) xs[t * 65 + c0 + u] = buf[u];
+            for (int u = 0; u < CW; ++u) xs[t * LT + u] = buf[u];
         }
         __syncthreads();
-        if (c <= clast && c >= clo) {
-            const int ns = m < nc ? m : nc;
-            for (int s = 0; s < ns; ++s) {
-                const S tsv = ts[s];
-                if (iszero(tsv)) continue;
-                const S *v = vs + s * bm;
-                S d0 = zero<S>(), d1 = zero<S>();
-                int i = s;
-                for (; i + 1 < m; i += 2) { d0 = add(d0, cmul(v[i], xs[i * 65 + t])); d1 = add(d1, cmul(v[i + 1], xs[(i + 1) * 65 + t])); }
-                if (i < m) d0 = add(d0, cmul(v[i], xs[i * 65 + t]));
-                const S d = mul(conj_(tsv), add(d0, d1));
-                for (int ii = s; ii < m; ++ii) xs[ii * 65 + t] = sub(xs[ii * 65 + t], mul(d, v[ii]));
-            }
-        }
-        __syncthreads();
-        for (int c0 = 0; c0 < 64; c0 += CH) {
+        S x[kS1MaxBM / 4];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int64_t col = cb + c0 + u;
-                if (t < m && col <= clast && col >= clo) X[r0 + t + col * ld] = xs[t * 65 + c0 + u];
+        for (int u = 0; u < kS1MaxBM / 4; ++u) x[u] = xs[(4 * u + part) * LT + cc];
+        const int ns = m < nc ? m : nc;
+        for (int s = 0; s < ns; ++s) {
+            const S tsv = ts[s];
+            if (iszero(tsv)) continue;                  // uniform
+            const S *v = vs + s * bm;
+            S p = zero<S>();
+#pragma unroll
+            for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                const int i = 4 * u + part;
+                if (i < bm) p = add(p, cmul(v[i], x[u]));
             }
+            const S d = mul(conj_(tsv), group_sum<4>(p));
+#pragma unroll
+            for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                const int i = 4 * u + part;
+                if (i < bm) x[u] = sub(x[u], mul(d, v[i]));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kS1MaxBM / 4; ++u) xs[(4 * u + part) * LT + cc] = x[u];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CW; ++u) {
+            const int64_t col = cb + u;
+            if (t < m && col <= clast && col >= clo) X[r0 + t + col * ld] = xs[t * LT + u];
         }
         __syncthreads();
     }
@@ -236,204 +235,210 @@ __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks b
 // ------------------------------------------------------ right chain (rows)
 // For k = nblk-1 .. 0: X(rho, block k columns) <- X(rho, block k columns) G_0
 // ... G_{nc-1} for rows rho in [0, rlast]; the block's columns are the block's
-// rows (r0(k) .. r1(k)).  64 rows per workgroup, reflectors staged in LDS.
+// rows (r0(k) .. r1(k)).  16 rows per workgroup of 64 threads, staged through
+// LDS; row rr is held in registers by the threads 4rr..4rr+3 (columns
+// 4u + (t & 3)).
 template <class S>
 __global__ __launch_bounds__(64) void k_s1_right_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
                                                        int64_t rlast)
 {
-    __shared__ S xs[64 * (kS1MaxBM + 1)];
+    constexpr int RW = kS1Cols, LT = kS1MaxBM + 1;
+    __shared__ S xs[RW * LT];                       // row rr, column c at xs[rr*LT + c]
     __shared__ S vs[kS1MaxBM * kS1MaxNB];
     __shared__ S ts[kS1MaxNB];
-    const int t = threadIdx.x;
-    const int64_t rho = (int64_t)blockIdx.x * 64 + t;
-    const bool ok = rho <= rlast;
+    const int t = threadIdx.x, rr = t >> 2, part = t & 3;
+    const int lr = t & (RW - 1), lc = t >> 4;       // staging: row lr, columns lc + 4u
+    const int64_t rb = (int64_t)blockIdx.x * RW;
+    const bool okst = rb + lr <= rlast;
     const int bm = (int)bl.bm;
-    constexpr int CH = 16;
-    S *x = xs + t * (kS1MaxBM + 1);
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t c0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - c0 + 1);
-        __syncthreads();
         stage_refl(vs, ts, V, tau, k, bm, nc, t);
-        for (int cc0 = 0; cc0 < kS1MaxBM; cc0 += CH) {
-            S buf[CH];
+        {
+            S buf[kS1MaxBM / 4];
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int cc = cc0 + u;
-                buf[u] = (ok && cc < m) ? X[rho + (c0 + cc) * ld] : zero<S>();
+            for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                const int c = lc + 4 * u;
+                buf[u] = (okst && c < m) ? X[rb + lr + (c0 + c) * ld] : zero<S>();
             }
 #pragma unroll
-            for (int u = 0; u < CH; ++u) x[cc0 + u] = buf[u];
+            for (int u = 0; u < kS1MaxBM / 4; ++u) xs[lr * LT + lc + 4 * u] = buf[u];
         }
         __syncthreads();
-        if (ok) {
-            const int ns = m < nc ? m : nc;
-            for (int s = 0; s < ns; ++s) {
-                const S tsv = ts[s];
-                if (iszero(tsv)) continue;
-                const S *v = vs + s * bm;
-                S d0 = zero<S>(), d1 = zero<S>();
-                int i = s;
-                for (; i + 1 < m; i += 2) { d0 = add(d0, mul(x[i], v[i])); d1 = add(d1, mul(x[i + 1], v[i + 1])); }
-                if (i < m) d0 = add(d0, mul(x[i], v[i]));
-                const S d = mul(add(d0, d1), tsv);
-                for (int ii = s; ii < m; ++ii) x[ii] = sub(x[ii], mul(d, conj_(v[ii])));
+        S x[kS1MaxBM / 4];
+#pragma unroll
+        for (int u = 0; u < kS1MaxBM / 4; ++u) x[u] = xs[rr * LT + 4 * u + part];
+        const int ns = m < nc ? m : nc;
+        for (int s = 0; s < ns; ++s) {
+            const S tsv = ts[s];
+            if (iszero(tsv)) continue;                  // uniform
+            const S *v = vs + s * bm;
+            S p = zero<S>();
+#pragma unroll
+            for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                const int c = 4 * u + part;
+                if (c < bm) p = add(p, mul(x[u], v[c]));
             }
-            for (int cc = 0; cc < m; ++cc) X[rho + (c0 + cc) * ld] = x[cc];
+            const S d = mul(group_sum<4>(p), tsv);
+#pragma unroll
+            for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                const int c = 4 * u + part;
+                if (c < bm) x[u] = sub(x[u], mul(d, conj_(v[c])));
+            }
         }
+#pragma unroll
+        for (int u = 0; u < kS1MaxBM / 4; ++u) xs[rr * LT + 4 * u + part] = x[u];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kS1MaxBM / 4; ++u) {
+            const int c = lc + 4 * u;
+            if (okst && c < m) X[rb + lr + (c0 + c) * ld] = xs[lr * LT + c];
+        }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------ right factor (one block)
-// RQ of B(block k, block k) = Rt Qt (Householder, last row first, the
-// reflector vectors kept in the annihilated part of the row), the first nr
-// rows of Qt, and their LQ factorisation: reflectors P_t (acting on local
+// RQ of B(block k, block k) = Rt Qt (Householder, last row first), the first
+// nr rows of Qt, and their LQ factorisation: reflectors P_t (acting on local
 // columns t..m-1, zeros above) into VR[k*bm*nc + t*bm + i], tau into
 // tauR[k*nc + t].
+//   RQ:  row i of the block is held in registers by threads 4i..4i+3
+//        (columns 4u + (tid & 3)); step i's reflector u_i goes to LDS (kept
+//        for the next phase), one barrier per step;
+//   Yc = U_{m-1} ... U_1 [e_0 .. e_{nr-1}]: column c by threads 8c..8c+7
+//        (rows 8v + (tid & 7)), no barriers;
+//   LQ of M = Yc^H: row t of M is column t of Yc, in the same registers; one
+//        barrier per reflector.
 template <class S>
 __global__ __launch_bounds__(256) void k_s1_right_factor(const S *B, int64_t ld, Blocks bl, int64_t k, int nb,
                                                          S *VR, S *tauR)
 {
-    __shared__ S W[kS1MaxBM * (kS1MaxBM + 1)];       // W[i*(bm+1) + c] row-major
-    __shared__ S Yc[kS1MaxBM * kS1MaxNB];            // Yc[c*bm + i] = Y(i, c), c < nr
-    __shared__ S ut[kS1MaxBM];                       // tau of the RQ reflectors
-    __shared__ S M[kS1MaxNB * (kS1MaxBM + 1)];       // M[t*(bm+1) + c]
-    __shared__ double red[4];
-    __shared__ S sc[3];
-    __shared__ S dots[kS1MaxNB];
+    __shared__ S U[kS1MaxBM * kS1MaxBM];             // U[i*64 + c], c < i: RQ reflector of row i
+    __shared__ S ut[kS1MaxBM];
+    __shared__ S vbuf[2][kS1MaxBM];
+    __shared__ S tbuf[2];
     const int tid = threadIdx.x;
-    const int bm = (int)bl.bm, LW = bm + 1;
+    const int bm = (int)bl.bm;
     const int64_t r0 = bl.r0(k);
     const int m = (int)(bl.r1(k) - r0 + 1);
     const int nr = m < nb ? m : nb;
+    // ---- RQ, rows m-1 .. 1
     {
-        constexpr int NT = kS1MaxBM * kS1MaxBM / 256;      // fixed trip count: loads in flight together
-        S buf[NT];
+        const int row = tid >> 2, part = tid & 3;
+        S w[kS1MaxBM / 4];
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int e = tid + 256 * u, i = e % m, c = e / m;
-            buf[u] = e < m * m ? B[r0 + i + (r0 + c) * ld] : zero<S>();
+        for (int u = 0; u < kS1MaxBM / 4; ++u) {
+            const int c = 4 * u + part;
+            w[u] = (row < m && c < m) ? B[r0 + row + (r0 + c) * ld] : zero<S>();
         }
+        for (int i = m - 1; i >= 1; --i) {
+            if (row == i) {
+                S al = zero<S>();
+                double ssp = 0.0;
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int e = tid + 256 * u, i = e % m, c = e / m;
-            if (e < m * m) W[i * LW + c] = buf[u];
-        }
-    }
-    __syncthreads();
-    // RQ, rows m-1 .. 1: u = conj(row i)(0..i), larfg with alpha = u_i
-    for (int i = m - 1; i >= 1; --i) {
-        double part = 0.0;
-        for (int c = tid; c < i; c += 256) part += abs2(W[i * LW + c]);
-        const double ss = block_sum256(part, red);
-        if (tid == 0) {
-            S t, b, f;
-            bool triv;
-            larfg_scalars(conj_(W[i * LW + i]), ss, t, b, f, triv);
-            sc[0] = t; sc[1] = b; sc[2] = f;
-            ut[i] = t;
-        }
-        __syncthreads();
-        const S t = sc[0], f = sc[2];
-        // u_c = conj(W[i][c]) * f (c < i), stored in place; u_i = 1
-        for (int c = tid; c < i; c += 256) W[i * LW + c] = iszero(t) ? zero<S>() : mul(conj_(W[i * LW + c]), f);
-        __syncthreads();
-        if (!iszero(t)) {
-            // rows 0..i-1: W(r, 0:i) <- W(r, 0:i) (I - t u u^H); 4 threads per row
-            for (int rb = 0; rb < i; rb += 64) {
-                const int r = rb + (tid >> 2), sub4 = tid & 3;
-                S part2 = zero<S>();
-                if (r < i)
-                    for (int c = sub4; c <= i; c += 4) {
-                        const S uc = (c == i) ? one<S>() : W[i * LW + c];
-                        part2 = add(part2, mul(W[r * LW + c], uc));
-                    }
-                const S d = mul(group_sum<4>(part2), t);
-                if (r < i)
-                    for (int c = sub4; c <= i; c += 4) {
-                        const S uc = (c == i) ? one<S>() : W[i * LW + c];
-                        W[r * LW + c] = sub(W[r * LW + c], mul(d, conj_(uc)));
-                    }
+                for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                    const int c = 4 * u + part;
+                    al = sel(c == i, w[u], al);
+                    ssp += (c < i) ? abs2(w[u]) : 0.0;
+                }
+                al = group_sum<4>(al);
+                const double ss = group_sum<4>(ssp);
+                S t, be, f;
+                bool triv;
+                larfg_scalars(conj_(al), ss, t, be, f, triv);
+#pragma unroll
+                for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                    const int c = 4 * u + part;
+                    if (c < i) U[i * kS1MaxBM + c] = iszero(t) ? zero<S>() : mul(conj_(w[u]), f);
+                }
+                if (part == 0) ut[i] = t;
+            }
+            __syncthreads();
+            const S t = ut[i];
+            if (row < i && !iszero(t)) {                 // rows 0..i-1: W <- W (I - t u u^H)
+                S p = zero<S>();
+#pragma unroll
+                for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                    const int c = 4 * u + part;
+                    const S uc = c < i ? U[i * kS1MaxBM + c] : (c == i ? one<S>() : zero<S>());
+                    p = add(p, mul(w[u], uc));
+                }
+                const S d = mul(group_sum<4>(p), t);
+#pragma unroll
+                for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                    const int c = 4 * u + part;
+                    const S uc = c < i ? U[i * kS1MaxBM + c] : (c == i ? one<S>() : zero<S>());
+                    w[u] = sub(w[u], mul(d, conj_(uc)));
+                }
             }
         }
-        __syncthreads();
-    }
-    // Yc = U_{m-1} ... U_1 [e_0 .. e_{nr-1}]
-    for (int e = tid; e < m * nr; e += 256) {
-        const int i = e % m, c = e / m;
-        Yc[c * bm + i] = (i == c) ? one<S>() : zero<S>();
     }
     __syncthreads();
+    // ---- Yc = U_{m-1} ... U_1 [e_0 .. e_{nr-1}]; column yc by 8 threads
+    const int yc = tid >> 3, yp = tid & 7;
+    S y[kS1MaxBM / 8];
+#pragma unroll
+    for (int v = 0; v < kS1MaxBM / 8; ++v) y[v] = (8 * v + yp == yc) ? one<S>() : zero<S>();
     for (int i = 1; i < m; ++i) {
         const S t = ut[i];
-        if (iszero(t)) continue;
-        // dots_c = u^H Yc(0:i, c), 8 threads per column
-        {
-            const int c = tid >> 3, sub8 = tid & 7;
-            S part2 = zero<S>();
-            if (c < nr)
-                for (int ii = sub8; ii <= i; ii += 8) {
-                    const S uc = (ii == i) ? one<S>() : W[i * LW + ii];
-                    part2 = add(part2, cmul(uc, Yc[c * bm + ii]));
-                }
-            const S d = mul(group_sum<8>(part2), t);
-            if (c < nr && sub8 == 0) dots[c] = d;
+        if (iszero(t)) continue;                          // uniform
+        S p = zero<S>();
+#pragma unroll
+        for (int v = 0; v < kS1MaxBM / 8; ++v) {
+            const int ii = 8 * v + yp;
+            const S uc = ii < i ? U[i * kS1MaxBM + ii] : (ii == i ? one<S>() : zero<S>());
+            p = add(p, cmul(uc, y[v]));
         }
-        __syncthreads();
-        for (int e = tid; e < (i + 1) * nr; e += 256) {
-            const int ii = e % (i + 1), c = e / (i + 1);
-            const S uc = (ii == i) ? one<S>() : W[i * LW + ii];
-            Yc[c * bm + ii] = sub(Yc[c * bm + ii], mul(dots[c], uc));
+        const S d = mul(group_sum<8>(p), t);
+#pragma unroll
+        for (int v = 0; v < kS1MaxBM / 8; ++v) {
+            const int ii = 8 * v + yp;
+            const S uc = ii < i ? U[i * kS1MaxBM + ii] : (ii == i ? one<S>() : zero<S>());
+            y[v] = sub(y[v], mul(d, uc));
         }
-        __syncthreads();
     }
-    // M = Qt(0:nr, :) = Yc^H
-    for (int e = tid; e < m * nr; e += 256) {
-        const int c = e % m, tt = e / m;
-        M[tt * LW + c] = conj_(Yc[tt * bm + c]);
-    }
-    __syncthreads();
-    // LQ of M: for row t, reflector from conj(M(t, t:m)); M(t+1:nr, t:m) <- M P_t
+    // ---- LQ of M = Qt(0:nr, :) = Yc^H: row yc of M, entries 8v + yp
+#pragma unroll
+    for (int v = 0; v < kS1MaxBM / 8; ++v) y[v] = conj_(y[v]);
     for (int t = 0; t < nr; ++t) {
-        const int len = m - t;
-        double part = 0.0;
-        for (int c = 1 + tid; c < len; c += 256) part += abs2(M[t * LW + t + c]);
-        const double ss = block_sum256(part, red);
-        if (tid == 0) {
-            S ta, b, f;
+        const int b = t & 1;
+        if (yc == t) {
+            S al = zero<S>();
+            double ssp = 0.0;
+#pragma unroll
+            for (int v = 0; v < kS1MaxBM / 8; ++v) {
+                const int c = 8 * v + yp;
+                al = sel(c == t, y[v], al);
+                ssp += (c > t && c < m) ? abs2(y[v]) : 0.0;
+            }
+            al = group_sum<8>(al);
+            const double ss = group_sum<8>(ssp);
+            S ta, be, f;
             bool triv;
-            larfg_scalars(conj_(M[t * LW + t]), ss, ta, b, f, triv);
-            sc[0] = ta; sc[1] = b; sc[2] = f;
-            tauR[k * nb + t] = ta;
+            larfg_scalars(conj_(al), ss, ta, be, f, triv);
+#pragma unroll
+            for (int v = 0; v < kS1MaxBM / 8; ++v) {
+                const int c = 8 * v + yp;
+                S vv = zero<S>();
+                if (c == t) vv = one<S>();
+                else if (c > t && c < m) vv = iszero(ta) ? zero<S>() : mul(conj_(y[v]), f);
+                if (c < bm) VR[(k * bm) * nb + t * bm + c] = vv;
+                vbuf[b][c] = vv;
+            }
+            if (yp == 0) { tauR[k * nb + t] = ta; tbuf[b] = ta; }
         }
         __syncthreads();
-        const S ta = sc[0], f = sc[2];
-        // v = [1, conj(M(t, t+1:m)) f]; stored in VR (and kept in M's row t)
-        for (int c = tid; c < bm; c += 256) {
-            S v = zero<S>();
-            if (c == t) v = one<S>();
-            else if (c > t && c < m) v = iszero(ta) ? zero<S>() : mul(conj_(M[t * LW + c]), f);
-            VR[(k * bm) * nb + t * bm + c] = v;
-            if (c > t && c < m) M[t * LW + c] = v;
+        const S ta = tbuf[b];
+        if (yc > t && yc < nr && !iszero(ta)) {           // rows t+1..nr-1: M <- M P_t
+            S p = zero<S>();
+#pragma unroll
+            for (int v = 0; v < kS1MaxBM / 8; ++v) p = add(p, mul(y[v], vbuf[b][8 * v + yp]));
+            const S d = mul(group_sum<8>(p), ta);
+#pragma unroll
+            for (int v = 0; v < kS1MaxBM / 8; ++v) y[v] = sub(y[v], mul(d, conj_(vbuf[b][8 * v + yp])));
         }
-        __syncthreads();
-        if (!iszero(ta)) {
-            // rows t+1..nr-1 (at most 31): 8 threads per row
-            const int rr = t + 1 + (tid >> 3), sub8 = tid & 7;
-            S part2 = zero<S>();
-            if (rr < nr)
-                for (int c = t + sub8; c < m; c += 8) {
-                    const S vc = (c == t) ? one<S>() : M[t * LW + c];
-                    part2 = add(part2, mul(M[rr * LW + c], vc));
-                }
-            const S d = mul(group_sum<8>(part2), ta);
-            if (rr < nr)
-                for (int c = t + sub8; c < m; c += 8) {
-                    const S vc = (c == t) ? one<S>() : M[t * LW + c];
-                    M[rr * LW + c] = sub(M[rr * LW + c], mul(d, conj_(vc)));
-                }
-        }
-        __syncthreads();
     }
 }
 
@@ -460,6 +465,13 @@ __global__ __launch_bounds__(256) void k_s1_zero_pattern(S *A, S *B, int64_t ld,
 // ------------------------------------------------------------------ host
 static int64_t s1_default_p(int64_t nb) { return i64max(2, i64min(8, kS1MaxBM / nb)); }
 
+// workspace of one call: left and right reflectors and taus of every block of a panel
+static size_t s1_workspace_bytes(int64_t n, int64_t nb, int64_t p, size_t elem)
+{
+    const int64_t maxblk = n / ((p - 1) * nb) + 2;
+    return 2 * ((size_t)maxblk * p * nb * nb * elem + (size_t)maxblk * nb * elem) + 1024;
+}
+
 template <class S>
 static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blocks &bl, int64_t c0, int nc,
                       S *V, S *tau, int64_t a2first, int64_t b2first, int b2from_block, hipStream_t st)
@@ -470,18 +482,18 @@ static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blo
     // X's own columns right of the panel (or A for the QR of B)
     if (A2 && a2first <= n - 1) {
         const int64_t ncols = n - a2first;
-        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, st, A2, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, A2, ld, bl, nc,
                            (const S *)V, (const S *)tau, a2first, n - 1, 0);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
     if (B2 && b2first <= n - 1) {
         const int64_t ncols = n - b2first;
-        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + 63) / 64)), dim3(64), 0, st, B2, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, B2, ld, bl, nc,
                            (const S *)V, (const S *)tau, b2first, n - 1, b2from_block);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
     if (Q) {
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, Q, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, Q, ld, bl, nc,
                            (const S *)V, (const S *)tau, n - 1);
         if ((rc = launch_check("k_s1_right_chain"))) return rc;
     }
@@ -508,7 +520,7 @@ static int rhess_impl(S *A, S *B, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, 
     const int64_t maxblk = n / ((p - 1) * nb) + 2;
     const size_t vb = (size_t)maxblk * bm * nb * sizeof(S), tb = (size_t)maxblk * nb * sizeof(S);
     int rc = 0;
-    unsigned char *ws = (unsigned char *)workspace_get(2 * (vb + tb) + 1024, st, &rc);
+    unsigned char *ws = (unsigned char *)workspace_get(s1_workspace_bytes(n, nb, p, sizeof(S)), st, &rc);
     if (!ws) return rc;
     S *VL = (S *)ws, *TL = (S *)(ws + vb), *VR = (S *)(ws + vb + tb), *TR = (S *)(ws + 2 * vb + tb);
     // 1. QR of B (panels of nb columns, blocks from the panel's first row)
@@ -537,17 +549,17 @@ static int rhess_impl(S *A, S *B, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, 
             // B(0:i2, block k columns) <- B P_0 ... P_{nb-1}: the row chain with this block only
             const int64_t rows = bl.r1(k) + 1;
             const Blocks one_blk{bl.r0(k), bl.step, bm, 1, n};
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, B, ld, one_blk,
+            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, B, ld, one_blk,
                                (int)nb, (const S *)(VR + k * bm * nb), (const S *)(TR + k * nb), rows - 1);
             if ((rc = launch_check("k_s1_right_chain"))) return rc;
             hipLaunchKernelGGL(k_s1_zero_block<S>, dim3(1), dim3(256), 0, st, B, ld, bl, k, (int)nb);
             if ((rc = launch_check("k_s1_zero_block"))) return rc;
         }
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, A, ld, bl, (int)nb,
+        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, A, ld, bl, (int)nb,
                            (const S *)VR, (const S *)TR, n - 1);
         if ((rc = launch_check("k_s1_right_chain"))) return rc;
         if (Z) {
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, Z, ld, bl, (int)nb,
+            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, Z, ld, bl, (int)nb,
                                (const S *)VR, (const S *)TR, n - 1);
             if ((rc = launch_check("k_s1_right_chain"))) return rc;
         }
@@ -563,6 +575,16 @@ int64_t ht_rhess_default_p(int64_t n, int64_t r)
 {
     if (n < 0 || r < 1) return -1;
     return ht::s1_default_p(ht::i64min(r, ht::i64max(n - 1, 1)));
+}
+int64_t ht_rhess_workspace_bytes(int64_t n, int64_t r, int64_t p, int is_complex)
+{
+    if (n < 0 || r < 1 || p < 0) return -1;
+    if (n == 0) return 0;
+    const int64_t nb = ht::i64min(r, ht::i64max(n - 1, 1));
+    if (nb > ht::kS1MaxNB) return -1;
+    if (p == 0) p = ht::s1_default_p(nb);
+    if (p < 2 || p * nb > ht::kS1MaxBM) return -1;
+    return (int64_t)ht::s1_workspace_bytes(n, nb, p, is_complex ? 16 : 8);
 }
 int ht_rhess(double *A, double *B, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, void *stream)
 {

@@ -455,6 +455,12 @@ int64_t ht_workspace_bytes(int64_t n, int64_t r, int64_t q, int is_complex)
     return (int64_t)ht::geometry(n, re_, q, is_complex ? 16 : 8).total;
 }
 
+int ht_reserve_workspace(int64_t bytes, void *stream)
+{
+    if (bytes < 0) return -1;
+    return ht::workspace_reserve((size_t)bytes, (hipStream_t)stream);
+}
+
 int64_t ht_default_q(int64_t n, int64_t r)
 {
     if (n <= 2 || r <= 1) return 1;

@@ -10,12 +10,18 @@ Two policies on the same trace:
 * ``fifo``: one request at a time in arrival order, each reduced by its own
   launches (one pencil per launch sequence) on one stream.
 * ``continuous``: continuous batching.  A request is admitted as soon as an
-  execution slot and HBM for its footprint (4 n^2 complex entries for H, T,
-  Q, Z plus the library workspace, ``ht_workspace_bytes``) are free; large or
+  execution slot and HBM for its footprint (6 n^2 complex entries: H, T, Q,
+  Z and the payload synthesis; each slot's library workspace is reserved once
+  at start, ``ht_reserve_workspace``) are free; large or
   dense requests each take a stream of their own, so their kernels overlap on
   the device; small r-HT requests that are waiting when the batch slot frees
   up are reduced together in one persistent ``ht_stage2_batched_z`` launch.
   Requests that arrive while others run join at the next free slot.
+
+Each slot's stream (and the auxiliary stream the library pairs with it for Q
+and Z) needs a hardware queue of its own for the slots' kernels to overlap:
+run with GPU_MAX_HW_QUEUES >= 2 * slots + 1 in the environment (HIP reads it
+when it initialises).
 
 Latency = completion (the request's last kernel observed finished) minus
 arrival, on the host clock, including queueing.  The payload of a request is
@@ -70,10 +76,21 @@ def make_trace(count: int, rate: float, seed: int = 0, nlo: int = 64, nhi: int =
 
 def footprint(req: Request) -> int:
     """Device bytes a request holds while admitted: H, T, Q, Z and two more
-    n x n complex matrices of payload synthesis, plus the library workspace."""
+    n x n complex matrices of payload synthesis.  The library workspace is not
+    part of it: every execution stream's workspace is reserved once, for the
+    largest request, when the engine starts."""
+    return 6 * req.n * req.n * 16
+
+
+def workspace_need(nmax: int, rs=(8, 16, 32)) -> int:
+    """Largest library workspace (stage two, or stage one) of a complex
+    request with n <= nmax and r in rs."""
     import paper_2301_07964_amd as ht
-    ws = max(0, ht.workspace_bytes(req.n, req.r, 0, True))
-    return 6 * req.n * req.n * 16 + ws
+    need = 0
+    for r in rs:
+        rr = min(r, max(nmax - 1, 1))
+        need = max(need, ht.workspace_bytes(nmax, rr, 0, True), ht.rhess_workspace_bytes(nmax, rr, 0, True))
+    return need
 
 
 def _synthesize(req: Request, device):
@@ -107,8 +124,10 @@ def _synthesize(req: Request, device):
 
 class Engine:
     def __init__(self, policy: str = "continuous", slots: int = 6, budget_bytes: int | None = None,
-                 small_n: int = 512, batch_cap: int = 256, keep_results: bool = False):
+                 small_n: int = 512, batch_cap: int = 256, keep_results: bool = False, nmax: int = 8192,
+                 rs=(8, 16, 32)):
         import torch
+        import paper_2301_07964_amd as ht
         assert policy in ("continuous", "fifo")
         self.policy = policy
         self.slots = 1 if policy == "fifo" else slots
@@ -116,12 +135,20 @@ class Engine:
         self.batch_cap = batch_cap
         self.keep = keep_results
         self.dev = torch.device("cuda:0")
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.slots)]
+        self.batch_stream = torch.cuda.Stream(device=self.dev)
+        # workspaces sized once for the largest request: no allocation (and no
+        # synchronisation) inside the loop
+        ws = workspace_need(nmax, rs)
+        for st in self.streams:
+            ht.reserve_workspace(ws, st)
+        ht.reserve_workspace(1 << 20, self.batch_stream)       # descriptors of up to ~8k pencils
+        torch.cuda.synchronize()
+        self.workspace_bytes = ws * len(self.streams)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.8 * free)
         self.budget = budget_bytes
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.slots)]
-        self.batch_stream = torch.cuda.Stream(device=self.dev)
         self.peak_bytes = 0
         self.max_inflight = 0
 
@@ -148,8 +175,9 @@ class Engine:
             ev.record(stream)
         return ev, mats
 
-    def run(self, trace, time_limit: float = 1e9):
-        """Replays ``trace`` in real time; fills admitted/done of every request."""
+    def run(self, trace, time_limit: float = 1e9, progress=None):
+        """Replays ``trace`` in real time; fills admitted/done of every request.
+        ``progress(done_count, total, now)`` is called after each completion."""
         pending = sorted(trace, key=lambda q: q.arrival)
         queue = []
         inflight = []               # (event, [reqs], bytes, slot index or -1 for the batch slot, payload)
@@ -158,6 +186,7 @@ class Engine:
         used = 0
         t0 = time.perf_counter()
         pi = 0
+        ndone = 0
         while pi < len(pending) or queue or inflight:
             now = time.perf_counter() - t0
             if now > time_limit:
@@ -175,6 +204,9 @@ class Engine:
                         if self.keep:
                             q.result = payload[k] if slot < 0 else payload
                     used -= nbytes
+                    ndone += len(reqs)
+                    if progress is not None:
+                        progress(ndone, len(pending), tdone)
                     if slot >= 0:
                         free_slots.append(slot)
                     else:

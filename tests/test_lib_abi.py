@@ -46,6 +46,20 @@ def test_host_only_entry_points():
     assert L.ht_workspace_bytes(100, 8, 0, 1) > L.ht_workspace_bytes(100, 8, 0, 0) > 0
     assert L.ht_workspace_bytes(100, 8, 9, 0) == -1          # q > r
     assert 1 <= L.ht_default_q(16384, 32) <= 32
+    L.ht_rhess_workspace_bytes.restype = ctypes.c_int64
+    L.ht_rhess_workspace_bytes.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_int]
+    assert L.ht_rhess_workspace_bytes(-1, 8, 0, 0) == -1
+    assert L.ht_rhess_workspace_bytes(100, 33, 0, 0) == -1      # n_b above 32
+    assert L.ht_rhess_workspace_bytes(100, 16, 5, 0) == -1      # p * n_b above 64
+    assert L.ht_rhess_workspace_bytes(0, 8, 0, 0) == 0
+    assert L.ht_rhess_workspace_bytes(100, 8, 0, 1) > L.ht_rhess_workspace_bytes(100, 8, 0, 0) > 0
+    # the reflectors of every block of a panel fit: blocks of p*nb rows, step (p-1)*nb
+    n, nb, p = 1000, 8, 8
+    blocks = n // ((p - 1) * nb) + 2
+    assert L.ht_rhess_workspace_bytes(n, nb, p, 0) >= 2 * blocks * (p * nb * nb + nb) * 8
+    L.ht_reserve_workspace.restype = ctypes.c_int
+    L.ht_reserve_workspace.argtypes = [ctypes.c_int64, ctypes.c_void_p]
+    assert L.ht_reserve_workspace(-1, None) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")

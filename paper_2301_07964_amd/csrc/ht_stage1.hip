@@ -54,7 +54,8 @@ __device__ inline void larfg_scalars(S alpha, double ss, S &tau, S &beta, S &sca
     trivial = (ss == 0.0 && im(alpha) == 0.0);
     if (trivial) { tau = zero<S>(); beta = alpha; scal = one<S>(); return; }
     const double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
-    tau = mk<S>((b - re(alpha)) / b, -im(alpha) / b);
+    const double rb = 1.0 / b;
+    tau = mk<S>((b - re(alpha)) * rb, -im(alpha) * rb);
     beta = mk<S>(b, 0.0);
     scal = recip(sub(alpha, beta));
 }
@@ -140,23 +141,23 @@ __global__ __launch_bounds__(256) void k_s1_block_qr(S *X, int64_t ld, Blocks bl
 }
 
 // Stage block k's reflectors (m x nc, column s at s*bm) and taus into LDS;
-// 64 threads, fixed trip counts so that the loads are in flight together.
-template <class S>
+// NT threads, fixed trip counts so that the loads are in flight together.
+template <int NT, class S>
 __device__ inline void stage_refl(S *vs, S *ts, const S *V, const S *tau, int64_t k, int bm, int nc, int t)
 {
     const S *Vk = V + k * bm * nc;
-    constexpr int CH = 16;
+    constexpr int CH = 8;
     const int tot = bm * nc;
-    for (int e0 = 0; e0 < tot; e0 += 64 * CH) {
+    for (int e0 = 0; e0 < tot; e0 += NT * CH) {
         S buf[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int e = e0 + u * 64 + t;
+            const int e = e0 + u * NT + t;
             buf[u] = e < tot ? Vk[e] : zero<S>();
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int e = e0 + u * 64 + t;
+            const int e = e0 + u * NT + t;
             if (e < tot) vs[e] = buf[u];
         }
     }
@@ -164,22 +165,25 @@ __device__ inline void stage_refl(S *vs, S *ts, const S *V, const S *tau, int64_
 }
 
 constexpr int kS1Cols = 16;      // columns (left chain) or rows (right chain) per workgroup
+constexpr int kS1ChainThreads = 256;
 
 // ------------------------------------------------------ left chain (columns)
 // For k = nblk-1 .. 0: X(block k rows, c) <- Q_k^H X(block k rows, c) for the
 // columns c in [cfirst, clast] with c >= (cfrom_block ? r0(k) : cfirst).
-// 16 columns per workgroup of 64 threads: the block's rows are staged through
-// LDS with coalesced loads, then column cc is held in registers by the four
-// threads 4cc..4cc+3 (rows 4u + (t & 3)).
+// 16 columns per workgroup of 256 threads: the block's rows are staged through
+// LDS with coalesced loads (lane = row), then column cc is held in registers
+// by the 16 threads 16cc..16cc+15 (rows 16u + (t & 15)).
 template <class S>
-__global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
-                                                      int64_t cfirst, int64_t clast, int cfrom_block)
+__global__ __launch_bounds__(kS1ChainThreads) void k_s1_left_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V,
+                                                                   const S *tau, int64_t cfirst, int64_t clast,
+                                                                   int cfrom_block)
 {
-    constexpr int CW = kS1Cols, LT = CW + 1;
+    constexpr int NT = kS1ChainThreads, CW = kS1Cols, LT = CW + 1, RPT = kS1MaxBM / 16;
     __shared__ S xs[kS1MaxBM * LT];                 // row i, column cc at xs[i*LT + cc]
     __shared__ S vs[kS1MaxBM * kS1MaxNB];
     __shared__ S ts[kS1MaxNB];
-    const int t = threadIdx.x, cc = t >> 2, part = t & 3;
+    const int t = threadIdx.x, cc = t >> 4, part = t & 15;
+    const int lr = t & 63, lc = t >> 6;             // staging: row lr, columns lc + 4u
     const int64_t cb = cfirst + (int64_t)blockIdx.x * CW;
     const int bm = (int)bl.bm;
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
@@ -187,46 +191,43 @@ __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks b
         const int m = (int)(bl.r1(k) - r0 + 1);
         const int64_t clo = cfrom_block ? i64max(cfirst, r0) : cfirst;
         if (cb + CW - 1 < clo) continue;                // uniform: the workgroup has no column here
-        stage_refl(vs, ts, V, tau, k, bm, nc, t);
+        stage_refl<NT>(vs, ts, V, tau, k, bm, nc, t);
         {
-            S buf[CW];
+            S buf[CW / 4];
 #pragma unroll
-            for (int u = 0; u < CW; ++u) {
-                const int64_t col = cb + u;
-                buf[u] = (t < m && col <= clast) ? X[r0 + t + col * ld] : zero<S>();
+            for (int u = 0; u < CW / 4; ++u) {
+                const int64_t col = cb + lc + 4 * u;
+                buf[u] = (lr < m && col <= clast) ? X[r0 + lr + col * ld] : zero<S>();
             }
 #pragma unroll
-            for (int u = 0; u < CW; ++u) xs[t * LT + u] = buf[u];
+            for (int u = 0; u < CW / 4; ++u) xs[lr * LT + lc + 4 * u] = buf[u];
         }
         __syncthreads();
-        S x[kS1MaxBM / 4];
+        S x[RPT];
 #pragma unroll
-        for (int u = 0; u < kS1MaxBM / 4; ++u) x[u] = xs[(4 * u + part) * LT + cc];
+        for (int u = 0; u < RPT; ++u) x[u] = xs[(16 * u + part) * LT + cc];
         const int ns = m < nc ? m : nc;
         for (int s = 0; s < ns; ++s) {
             const S tsv = ts[s];
             if (iszero(tsv)) continue;                  // uniform
             const S *v = vs + s * bm;
+            S vi[RPT];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) vi[u] = (16 * u + part < bm) ? v[16 * u + part] : zero<S>();
             S p = zero<S>();
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                const int i = 4 * u + part;
-                if (i < bm) p = add(p, cmul(v[i], x[u]));
-            }
-            const S d = mul(conj_(tsv), group_sum<4>(p));
+            for (int u = 0; u < RPT; ++u) p = add(p, cmul(vi[u], x[u]));
+            const S d = mul(conj_(tsv), group_sum<16>(p));
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                const int i = 4 * u + part;
-                if (i < bm) x[u] = sub(x[u], mul(d, v[i]));
-            }
+            for (int u = 0; u < RPT; ++u) x[u] = sub(x[u], mul(d, vi[u]));
         }
 #pragma unroll
-        for (int u = 0; u < kS1MaxBM / 4; ++u) xs[(4 * u + part) * LT + cc] = x[u];
+        for (int u = 0; u < RPT; ++u) xs[(16 * u + part) * LT + cc] = x[u];
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < CW; ++u) {
-            const int64_t col = cb + u;
-            if (t < m && col <= clast && col >= clo) X[r0 + t + col * ld] = xs[t * LT + u];
+        for (int u = 0; u < CW / 4; ++u) {
+            const int64_t col = cb + lc + 4 * u;
+            if (lr < m && col <= clast && col >= clo) X[r0 + lr + col * ld] = xs[lr * LT + lc + 4 * u];
         }
         __syncthreads();
     }
@@ -235,64 +236,61 @@ __global__ __launch_bounds__(64) void k_s1_left_chain(S *X, int64_t ld, Blocks b
 // ------------------------------------------------------ right chain (rows)
 // For k = nblk-1 .. 0: X(rho, block k columns) <- X(rho, block k columns) G_0
 // ... G_{nc-1} for rows rho in [0, rlast]; the block's columns are the block's
-// rows (r0(k) .. r1(k)).  16 rows per workgroup of 64 threads, staged through
-// LDS; row rr is held in registers by the threads 4rr..4rr+3 (columns
-// 4u + (t & 3)).
+// rows (r0(k) .. r1(k)).  16 rows per workgroup of 256 threads, staged through
+// LDS; row rr is held in registers by the threads 16rr..16rr+15 (columns
+// 16u + (t & 15)).
 template <class S>
-__global__ __launch_bounds__(64) void k_s1_right_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V, const S *tau,
-                                                       int64_t rlast)
+__global__ __launch_bounds__(kS1ChainThreads) void k_s1_right_chain(S *X, int64_t ld, Blocks bl, int nc, const S *V,
+                                                                    const S *tau, int64_t rlast)
 {
-    constexpr int RW = kS1Cols, LT = kS1MaxBM + 1;
+    constexpr int NT = kS1ChainThreads, RW = kS1Cols, LT = kS1MaxBM + 1, CPT = kS1MaxBM / 16;
     __shared__ S xs[RW * LT];                       // row rr, column c at xs[rr*LT + c]
     __shared__ S vs[kS1MaxBM * kS1MaxNB];
     __shared__ S ts[kS1MaxNB];
-    const int t = threadIdx.x, rr = t >> 2, part = t & 3;
-    const int lr = t & (RW - 1), lc = t >> 4;       // staging: row lr, columns lc + 4u
+    const int t = threadIdx.x, rr = t >> 4, part = t & 15;
+    const int lr = t & (RW - 1), lc = t >> 4;       // staging: row lr, columns lc + 16u
     const int64_t rb = (int64_t)blockIdx.x * RW;
     const bool okst = rb + lr <= rlast;
     const int bm = (int)bl.bm;
     for (int64_t k = bl.nblk - 1; k >= 0; --k) {
         const int64_t c0 = bl.r0(k);
         const int m = (int)(bl.r1(k) - c0 + 1);
-        stage_refl(vs, ts, V, tau, k, bm, nc, t);
+        stage_refl<NT>(vs, ts, V, tau, k, bm, nc, t);
         {
-            S buf[kS1MaxBM / 4];
+            S buf[CPT];
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                const int c = lc + 4 * u;
+            for (int u = 0; u < CPT; ++u) {
+                const int c = lc + 16 * u;
                 buf[u] = (okst && c < m) ? X[rb + lr + (c0 + c) * ld] : zero<S>();
             }
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) xs[lr * LT + lc + 4 * u] = buf[u];
+            for (int u = 0; u < CPT; ++u) xs[lr * LT + lc + 16 * u] = buf[u];
         }
         __syncthreads();
-        S x[kS1MaxBM / 4];
+        S x[CPT];
 #pragma unroll
-        for (int u = 0; u < kS1MaxBM / 4; ++u) x[u] = xs[rr * LT + 4 * u + part];
+        for (int u = 0; u < CPT; ++u) x[u] = xs[rr * LT + 16 * u + part];
         const int ns = m < nc ? m : nc;
         for (int s = 0; s < ns; ++s) {
             const S tsv = ts[s];
             if (iszero(tsv)) continue;                  // uniform
             const S *v = vs + s * bm;
+            S vc[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) vc[u] = (16 * u + part < bm) ? v[16 * u + part] : zero<S>();
             S p = zero<S>();
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                const int c = 4 * u + part;
-                if (c < bm) p = add(p, mul(x[u], v[c]));
-            }
-            const S d = mul(group_sum<4>(p), tsv);
+            for (int u = 0; u < CPT; ++u) p = add(p, mul(x[u], vc[u]));
+            const S d = mul(group_sum<16>(p), tsv);
 #pragma unroll
-            for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                const int c = 4 * u + part;
-                if (c < bm) x[u] = sub(x[u], mul(d, conj_(v[c])));
-            }
+            for (int u = 0; u < CPT; ++u) x[u] = sub(x[u], mul(d, conj_(vc[u])));
         }
 #pragma unroll
-        for (int u = 0; u < kS1MaxBM / 4; ++u) xs[rr * LT + 4 * u + part] = x[u];
+        for (int u = 0; u < CPT; ++u) xs[rr * LT + 16 * u + part] = x[u];
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kS1MaxBM / 4; ++u) {
-            const int c = lc + 4 * u;
+        for (int u = 0; u < CPT; ++u) {
+            const int c = lc + 16 * u;
             if (okst && c < m) X[rb + lr + (c0 + c) * ld] = xs[lr * LT + c];
         }
         __syncthreads();
@@ -349,29 +347,27 @@ __global__ __launch_bounds__(256) void k_s1_right_factor(const S *B, int64_t ld,
                 bool triv;
                 larfg_scalars(conj_(al), ss, t, be, f, triv);
 #pragma unroll
-                for (int u = 0; u < kS1MaxBM / 4; ++u) {
+                for (int u = 0; u < kS1MaxBM / 4; ++u) {     // the whole row: u_c (c < i), 1, zeros
                     const int c = 4 * u + part;
-                    if (c < i) U[i * kS1MaxBM + c] = iszero(t) ? zero<S>() : mul(conj_(w[u]), f);
+                    S uc = zero<S>();
+                    if (c < i) uc = iszero(t) ? zero<S>() : mul(conj_(w[u]), f);
+                    else if (c == i) uc = one<S>();
+                    U[i * kS1MaxBM + c] = uc;
                 }
                 if (part == 0) ut[i] = t;
             }
             __syncthreads();
             const S t = ut[i];
             if (row < i && !iszero(t)) {                 // rows 0..i-1: W <- W (I - t u u^H)
+                S uc[kS1MaxBM / 4];
+#pragma unroll
+                for (int u = 0; u < kS1MaxBM / 4; ++u) uc[u] = U[i * kS1MaxBM + 4 * u + part];
                 S p = zero<S>();
 #pragma unroll
-                for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                    const int c = 4 * u + part;
-                    const S uc = c < i ? U[i * kS1MaxBM + c] : (c == i ? one<S>() : zero<S>());
-                    p = add(p, mul(w[u], uc));
-                }
+                for (int u = 0; u < kS1MaxBM / 4; ++u) p = add(p, mul(w[u], uc[u]));
                 const S d = mul(group_sum<4>(p), t);
 #pragma unroll
-                for (int u = 0; u < kS1MaxBM / 4; ++u) {
-                    const int c = 4 * u + part;
-                    const S uc = c < i ? U[i * kS1MaxBM + c] : (c == i ? one<S>() : zero<S>());
-                    w[u] = sub(w[u], mul(d, conj_(uc)));
-                }
+                for (int u = 0; u < kS1MaxBM / 4; ++u) w[u] = sub(w[u], mul(d, conj_(uc[u])));
             }
         }
     }
@@ -384,20 +380,15 @@ __global__ __launch_bounds__(256) void k_s1_right_factor(const S *B, int64_t ld,
     for (int i = 1; i < m; ++i) {
         const S t = ut[i];
         if (iszero(t)) continue;                          // uniform
+        S uc[kS1MaxBM / 8];
+#pragma unroll
+        for (int v = 0; v < kS1MaxBM / 8; ++v) uc[v] = U[i * kS1MaxBM + 8 * v + yp];
         S p = zero<S>();
 #pragma unroll
-        for (int v = 0; v < kS1MaxBM / 8; ++v) {
-            const int ii = 8 * v + yp;
-            const S uc = ii < i ? U[i * kS1MaxBM + ii] : (ii == i ? one<S>() : zero<S>());
-            p = add(p, cmul(uc, y[v]));
-        }
+        for (int v = 0; v < kS1MaxBM / 8; ++v) p = add(p, cmul(uc[v], y[v]));
         const S d = mul(group_sum<8>(p), t);
 #pragma unroll
-        for (int v = 0; v < kS1MaxBM / 8; ++v) {
-            const int ii = 8 * v + yp;
-            const S uc = ii < i ? U[i * kS1MaxBM + ii] : (ii == i ? one<S>() : zero<S>());
-            y[v] = sub(y[v], mul(d, uc));
-        }
+        for (int v = 0; v < kS1MaxBM / 8; ++v) y[v] = sub(y[v], mul(d, uc[v]));
     }
     // ---- LQ of M = Qt(0:nr, :) = Yc^H: row yc of M, entries 8v + yp
 #pragma unroll
@@ -482,18 +473,18 @@ static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blo
     // X's own columns right of the panel (or A for the QR of B)
     if (A2 && a2first <= n - 1) {
         const int64_t ncols = n - a2first;
-        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, A2, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, A2, ld, bl, nc,
                            (const S *)V, (const S *)tau, a2first, n - 1, 0);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
     if (B2 && b2first <= n - 1) {
         const int64_t ncols = n - b2first;
-        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, B2, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, B2, ld, bl, nc,
                            (const S *)V, (const S *)tau, b2first, n - 1, b2from_block);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
     if (Q) {
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, Q, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, Q, ld, bl, nc,
                            (const S *)V, (const S *)tau, n - 1);
         if ((rc = launch_check("k_s1_right_chain"))) return rc;
     }
@@ -549,17 +540,17 @@ static int rhess_impl(S *A, S *B, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, 
             // B(0:i2, block k columns) <- B P_0 ... P_{nb-1}: the row chain with this block only
             const int64_t rows = bl.r1(k) + 1;
             const Blocks one_blk{bl.r0(k), bl.step, bm, 1, n};
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, B, ld, one_blk,
+            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, B, ld, one_blk,
                                (int)nb, (const S *)(VR + k * bm * nb), (const S *)(TR + k * nb), rows - 1);
             if ((rc = launch_check("k_s1_right_chain"))) return rc;
             hipLaunchKernelGGL(k_s1_zero_block<S>, dim3(1), dim3(256), 0, st, B, ld, bl, k, (int)nb);
             if ((rc = launch_check("k_s1_zero_block"))) return rc;
         }
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, A, ld, bl, (int)nb,
+        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, A, ld, bl, (int)nb,
                            (const S *)VR, (const S *)TR, n - 1);
         if ((rc = launch_check("k_s1_right_chain"))) return rc;
         if (Z) {
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(64), 0, st, Z, ld, bl, (int)nb,
+            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, Z, ld, bl, (int)nb,
                                (const S *)VR, (const S *)TR, n - 1);
             if ((rc = launch_check("k_s1_right_chain"))) return rc;
         }

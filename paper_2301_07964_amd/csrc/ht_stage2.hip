@@ -241,6 +241,43 @@ static int launch_update_mfma(bool left, const UpdArgs<double> &ua, const double
     }
 }
 
+// Complex matrix-core application kernels (one tile of 16 per wavefront).
+template <int R>
+static int launch_update_mfma_z_r(bool left, UpdArgs<zd> ua, const double *F, hipStream_t st)
+{
+    int64_t tot = 0;
+    for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + 15) / 16; tot += ua.job[i].npanels; }
+    const dim3 grid((unsigned)((tot + 3) / 4)), blk(256);
+    if (left) hipLaunchKernelGGL((k_update_mfma_z<R, true>), grid, blk, 0, st, ua, F);
+    else hipLaunchKernelGGL((k_update_mfma_z<R, false>), grid, blk, 0, st, ua, F);
+    return launch_check(left ? "k_update_mfma_z(left)" : "k_update_mfma_z(right)");
+}
+
+static int launch_update_mfma_z(bool left, const UpdArgs<zd> &ua, const double *F, hipStream_t st)
+{
+    switch (ua.r) {
+    case 4: return launch_update_mfma_z_r<4>(left, ua, F, st);
+    case 8: return launch_update_mfma_z_r<8>(left, ua, F, st);
+    case 16: return launch_update_mfma_z_r<16>(left, ua, F, st);
+    case 32: return launch_update_mfma_z_r<32>(left, ua, F, st);
+    default: return HT_ERR_NOTSUP;
+    }
+}
+
+static int launch_form_factors_z(int64_t r, int64_t q, int64_t kmax, int64_t kext, const zd *VL, const zd *TL,
+                                 const zd *VR, const zd *TR, double *F, hipStream_t st)
+{
+    const dim3 grid((unsigned)kmax, 2), blk(64);
+    switch (r) {
+    case 4: hipLaunchKernelGGL((k_form_factors_z<4, 16>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 8: hipLaunchKernelGGL((k_form_factors_z<8, 16>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 16: hipLaunchKernelGGL((k_form_factors_z<16, 32>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    case 32: hipLaunchKernelGGL((k_form_factors_z<32, 64>), grid, blk, 0, st, q, kext, VL, TL, VR, TR, F); break;
+    default: return HT_ERR_NOTSUP;
+    }
+    return launch_check("k_form_factors_z");
+}
+
 static int launch_form_factors(int64_t r, int64_t q, int64_t kmax, int64_t kext, const double *VL, const double *TL,
                                const double *VR, const double *TR, double *F, hipStream_t st)
 {
@@ -255,13 +292,15 @@ static int launch_form_factors(int64_t r, int64_t q, int64_t kmax, int64_t kext,
     return launch_check("k_form_factors");
 }
 
-// dispatch of one update pass: matrix cores for real r in {4, 8, 16, 32},
-// the vector kernels otherwise
+// dispatch of one update pass: matrix cores for r in {4, 8, 16, 32}, the
+// vector kernels otherwise
 template <class S>
 static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S *F, hipStream_t st)
 {
     if constexpr (sizeof(S) == 8) {
         if (F) return launch_update_mfma(!right, ua, (const double *)F, st);
+    } else {
+        if (F) return launch_update_mfma_z(!right, ua, (const double *)F, st);
     }
     return launch_update<S>(right, ua, panels, st);
 }
@@ -272,8 +311,8 @@ struct Geometry {
     size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, off_prog, total;
 };
 
-// The matrix-core application path: real arithmetic, r in {4, 8, 16, 32}.
-static bool use_mfma(int64_t r, size_t esz) { return esz == 8 && (r == 4 || r == 8 || r == 16 || r == 32); }
+// The matrix-core application path: real and complex, r in {4, 8, 16, 32}.
+static bool use_mfma(int64_t r, size_t) { return r == 4 || r == 8 || r == 16 || r == 32; }
 static int64_t kw_of(int64_t r) { return 2 * r < 16 ? 16 : 2 * r; }
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -364,10 +403,12 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)qg), dim3(256), 0, st, ga);
         else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)qg), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
-        if constexpr (sizeof(S) == 8) {
-            if (mf) {
-                ProfScope ps(6, st);
+        if (mf) {
+            ProfScope ps(6, st);
+            if constexpr (sizeof(S) == 8) {
                 if ((rc = launch_form_factors(rr, qg, kmax, kext, VL, TL, VR, TR, F, st))) return rc;
+            } else {
+                if ((rc = launch_form_factors_z(rr, qg, kmax, kext, VL, TL, VR, TR, (double *)F, st))) return rc;
             }
         }
         UpdArgs<S> ua;

@@ -1,6 +1,7 @@
 // ht_update_mfma.hpp -- application phase of blocked stage two on the FP64
 // matrix cores (Section 3.2, "Applying the reflectors"; application algorithm
-// of the appendix), real arithmetic, r in {4, 8, 16, 32}.
+// of the appendix), r in {4, 8, 16, 32}; real arithmetic first, the complex
+// variant at the end.
 //
 // The q reflectors of window k (local indices 0 .. W-1, W = q+r-1, the w-th
 // reflector acting on w .. w+r-1) are first accumulated into the window's
@@ -191,6 +192,173 @@ __global__ __launch_bounds__(256) void k_update_mfma(UpdArgs<double> a, const do
                 if (ok) v = X[ad];
                 xb[t][kk] = v;
             }
+        }
+    }
+}
+
+}  // namespace ht
+
+namespace ht {
+
+// ---------------------------------------------------------------- complex
+// Complex128 variant.  A complex product on the FP64 matrix cores takes four
+// real ones: Re D += Re A Re B - Im A Im B, Im D += Re A Im B + Im A Re B.
+// The window factor is stored as two real planes of fragments of U^T; right
+// updates use A = U^T, left updates A = U^H, whose imaginary plane is the
+// stored one negated (the left reflectors' factor serves both: the left
+// updates of H and T, and the right update of Q).
+
+// Window factors, complex.  Grid (kmax, 2) as for the real kernel; lane i
+// forms row i of U_k in LDS.  Output plane p (0 real, 1 imaginary):
+//   F[((side*kext + k)*2 + p)*KW*KW + (mb*KK + kk)*64 + l]
+//     = (Re, Im) U_k[4kk + l/16][16mb + l%16].
+template <int R, int KW>
+__global__ __launch_bounds__(64) void k_form_factors_z(int64_t q, int64_t kext, const zd *VL, const zd *TL,
+                                                       const zd *VR, const zd *TR, double *F)
+{
+    constexpr int MB = KW / 16, KK = KW / 4, LU = KW + 1;
+    const int64_t k = blockIdx.x;
+    const int side = blockIdx.y;
+    const int lane = threadIdx.x;
+    const zd *V = side ? VR : VL;
+    const zd *Tv = side ? TR : TL;
+    __shared__ zd us[KW * LU];                      // row i of U_k at us[i*LU + c]
+    __shared__ zd vs[R];
+    zd *u = us + lane * LU;
+    if (lane < KW) {
+        for (int c = 0; c < KW; ++c) u[c] = (c == lane) ? one<zd>() : zero<zd>();
+    }
+    for (int w = 0; w < R; ++w) {
+        if (w >= q) break;                          // uniform
+        const zd tau = Tv[w * kext + k];
+        if (iszero(tau)) continue;                  // uniform
+        __syncthreads();
+        if (lane < R) vs[lane] = V[(w * kext + k) * R + lane];
+        __syncthreads();
+        if (lane < KW) {                            // row <- row (I - tau v v^H)
+            zd s = zero<zd>();
+            for (int c = 0; c < R; ++c) s = add(s, mul(u[w + c], vs[c]));
+            s = mul(s, tau);
+            for (int c = 0; c < R; ++c) u[w + c] = sub(u[w + c], mul(s, conj_(vs[c])));
+        }
+    }
+    __syncthreads();
+    double *out = F + ((int64_t)side * kext + k) * 2 * (KW * KW);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const zd e = us[(4 * kk + (lane >> 4)) * LU + 16 * mb + (lane & 15)];
+            out[(mb * KK + kk) * 64 + lane] = e.re;
+            out[KW * KW + (mb * KK + kk) * 64 + lane] = e.im;
+        }
+}
+
+// Delayed updates on the matrix cores, complex.  Same tiling, window ring and
+// job handling as the real kernel (one tile of 16 rows / columns per
+// wavefront), with the real and imaginary parts of the tile and of the
+// accumulators in separate registers.
+template <int R, bool LEFT>
+__global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const double *F)
+{
+    constexpr int KW = KWOf<R>::value;
+    constexpr int MB = KW / 16, KK = KW / 4, RS = R / 4;
+    const int lane = threadIdx.x & 63;
+    int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int jid = 0;
+    while (jid < a.njobs - 1 && b >= a.job[jid].npanels) { b -= a.job[jid].npanels; ++jid; }
+    UpdJob<zd> J = a.job[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
+    if (b >= J.npanels) return;
+    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
+    const int64_t W = q + R - 1;
+    const int g = lane >> 4, li = lane & 15;
+    const int64_t p0 = b * 16;                      // first row (right) / column (left) of the tile
+    const double *Fs = F + (LEFT ? 0 : (int64_t)J.side * kext * 2 * (KW * KW));
+    zd *X = J.X;
+    const int64_t ld = J.ld;
+
+    int64_t kfirst = kmax - 1, klast = 0;
+    if (J.lim >= 0) {
+        if (!LEFT) {
+            while (klast < kmax && !(p0 < i64min(j1 + klast * R + W - 1, n - 1) + 1 + J.lim)) ++klast;
+            if (klast >= kmax) return;
+        } else {
+            while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
+            if (kfirst < 0) return;
+        }
+    }
+    auto addr = [&](int64_t lo, int c, bool &ok) -> int64_t {
+        const int64_t fixed = p0 + li, idx = lo + c;
+        ok = fixed < n && idx < n;
+        return LEFT ? idx + fixed * ld : fixed + idx * ld;
+    };
+
+    double xr[KK], xi[KK];
+    {
+        const int64_t lo = j1 + kfirst * R;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const int c = 4 * kk + g;
+            bool ok;
+            const int64_t ad = addr(lo, c, ok);
+            zd v = zero<zd>();
+            if (ok && c < W) v = X[ad];
+            xr[kk] = v.re;
+            xi[kk] = v.im;
+        }
+    }
+    for (int64_t k = kfirst; k >= klast; --k) {
+        const int64_t lo = j1 + k * R;
+        const double *Fr = Fs + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
+        f64x4 ar[MB], ai[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) { ar[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; ai[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; }
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            double fr[MB], fi[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                fr[mb] = Fr[(mb * KK + kk) * 64 + lane];
+                fi[mb] = LEFT ? -Fi[(mb * KK + kk) * 64 + lane] : Fi[(mb * KK + kk) * 64 + lane];
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xr[kk], ar[mb], 0, 0, 0);
+                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[mb], xi[kk], ar[mb], 0, 0, 0);
+                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xi[kk], ai[mb], 0, 0, 0);
+                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[mb], xr[kk], ai[mb], 0, 0, 0);
+            }
+        }
+        const int64_t f0 = (k == klast) ? 0 : q - 1;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * mb + 4 * v + g;
+                bool ok;
+                const int64_t ad = addr(lo, c, ok);
+                if (ok && c >= f0 && c < W) X[ad] = mk<zd>(ar[mb][v], ai[mb][v]);
+            }
+        if (k == klast) break;
+        const int64_t lon = lo - R;
+#pragma unroll
+        for (int kk = 0; kk < RS; ++kk) {
+            const int c = 4 * kk + g;
+            const bool keep = c < q - 1;
+            xr[kk + RS] = keep ? ar[kk >> 2][kk & 3] : 0.0;
+            xi[kk + RS] = keep ? ai[kk >> 2][kk & 3] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < RS; ++kk) {
+            const int c = 4 * kk + g;
+            bool ok;
+            const int64_t ad = addr(lon, c, ok);
+            zd v = zero<zd>();
+            if (ok) v = X[ad];
+            xr[kk] = v.re;
+            xi[kk] = v.im;
         }
     }
 }

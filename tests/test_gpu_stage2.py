@@ -69,10 +69,30 @@ def test_parity_group_sizes(q):
     check_parity(H, T, 8, q)
 
 
-@pytest.mark.parametrize("n,r,seed", [(150, 5, 0), (128, 8, 1), (70, 16, 2)])
+@pytest.mark.parametrize("n,r,seed", [(150, 5, 0), (128, 8, 1), (70, 16, 2), (90, 4, 4), (160, 32, 3), (300, 8, 5)])
 def test_parity_complex(n, r, seed):
     H, T = inputs.rht_pencil_complex(n, r, seed)
     check_parity(H, T, r)
+
+
+@pytest.mark.parametrize("n,r,seed", [(400, 16, 5), (400, 32, 5)])
+def test_parity_complex_at_the_sensitivity_floor(n, r, seed):
+    """Larger complex pencils of the generator are sensitive: the oracle's own
+    output moves by up to ~1e-7 when the band of H is perturbed by 1e-15
+    relative, so no implementation can meet 1e-9 there.  The GPU result must
+    then lie within 10x of that floor (and within 1e-9 where the floor is
+    below 1e-10)."""
+    from oracle import oracle as O
+    H, T = inputs.rht_pencil_complex(n, r, seed)
+    ref = O.stage2(H, T, r)
+    rng = np.random.default_rng(1)
+    P = rng.standard_normal(H.shape) + 1j * rng.standard_normal(H.shape)
+    ref2 = O.stage2(H + 1e-15 * np.abs(H) * P, T, r)
+    floor = max(rel(a, b) for a, b in zip(ref2[:4], ref[:4]))
+    got = run_gpu(H, T, r)
+    errs = [rel(g, o) for g, o in zip(got, ref[:4])]
+    print(f"[parity] n={n} r={r} complex: floor {floor:.2e}, errors {errs}", flush=True)
+    assert max(errs) <= max(1e-9, 10 * floor), (errs, floor)
 
 
 @pytest.mark.parametrize("n,r", [(0, 3), (1, 3), (2, 3), (3, 1), (3, 2), (5, 4), (12, 30), (40, 1)])
@@ -139,12 +159,12 @@ def _backward(Hin, Tin, r, q=0):
     return res
 
 
-@pytest.mark.parametrize("n,r", [(2048, 8), (4096, 16)])
-def test_backward_error_large(n, r):
+@pytest.mark.parametrize("n,r,cplx", [(2048, 8, False), (4096, 16, False), (2048, 32, True), (1500, 4, True)])
+def test_backward_error_large(n, r, cplx):
     """Invariants at sizes the oracle is too slow for: exact zeros, orthogonality and
     backward error within 100 n eps (eps = 2^-52)."""
-    print(f"[backward] n={n} r={r}", flush=True)
-    H, T = inputs.rht_pencil(n, r, 1)
+    print(f"[backward] n={n} r={r} complex={cplx}", flush=True)
+    H, T = (inputs.rht_pencil_complex if cplx else inputs.rht_pencil)(n, r, 1)
     res = _backward(H, T, r)
     bound = 100 * n * EPS
     assert res["zeros"], res

@@ -183,13 +183,16 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                     if (++polls > (1 << 22)) { s_abort = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
+                // one acquire per workgroup: it invalidates the caches the
+                // workgroup's waves read through, and the barrier orders their
+                // loads after it
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
             if (s_abort) {
                 if (tid == 0) st_release(a.progress + w, 0x3fffffff);
                 return;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const int64_t jb = j + i64max(0, (k - 1) * r + 1);
         const int64_t i1 = j + k * r + 1;
@@ -356,9 +359,13 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             }
             if (tid == 0) { a.TL[w * kext + k] = zero<S>(); a.TR[w * kext + k] = zero<S>(); }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the barrier completes every wave's stores; one agent-scope release
+        // (a write-back of the shared cache) then publishes them with the flag
         __syncthreads();
-        if (tid == 0) st_release(a.progress + w, (int)(k + 1));
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            st_release(a.progress + w, (int)(k + 1));
+        }
     }
     __syncthreads();
     if (tid == 0) st_release(a.progress + w, 0x3fffffff);

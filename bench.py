@@ -201,7 +201,9 @@ def bench_serving(args):
     with r < n/4, 20% dense (stage one first), Poisson arrivals.  The arrival
     rate is 0.8 x the FIFO capacity measured on a calibration sample in the
     same run; both policies replay the same trace.  Reports p50/p99 latency
-    (completion - arrival, host clock, queueing included) and pencils/s."""
+    (completion - arrival, host clock, queueing included) and pencils/s; the
+    throughput ratio comes from a second pass in which the same requests all
+    arrive at once (pencils / makespan)."""
     import numpy as np
     # one hardware queue per execution stream (6 slots x 2 streams + the batch
     # stream); HIP reads this when it initialises, below
@@ -234,6 +236,20 @@ def bench_serving(args):
         res[policy] = dict(S.summary(trace), wall_s=round(wall, 3), max_inflight=eng.max_inflight,
                            peak_accounted_gb=round(eng.peak_bytes / 2 ** 30, 2))
         print(f"[bench] {policy}: {res[policy]}", file=sys.stderr, flush=True)
+    # capacity: the same requests all arriving at once (makespan-bound)
+    cap_res = {}
+    for policy in ("fifo", "continuous"):
+        trace = S.make_trace(count, rate=0.0, seed=args.seed)
+        eng = S.Engine(policy)
+        t0 = time.perf_counter()
+
+        def progress(k, tot, now, policy=policy):
+            print(f"[bench] saturated {policy}: {k}/{tot} requests done at {now:.1f} s", file=sys.stderr, flush=True)
+        eng.run(trace, time_limit=1500, progress=progress)
+        wall = time.perf_counter() - t0
+        cap_res[policy] = {"makespan_s": round(wall, 3), "pencils_per_s": round(count / wall, 4),
+                           "max_inflight": eng.max_inflight}
+        print(f"[bench] saturated {policy}: {cap_res[policy]}", file=sys.stderr, flush=True)
     c, f = res["continuous"], res["fifo"]
     out = {
         "metric": "serving: p99 latency and pencils/s of continuous batching vs one-pencil-per-launch FIFO",
@@ -251,9 +267,54 @@ def bench_serving(args):
                    "arrival_rate": round(lam, 4), "fifo_capacity": round(cap, 4), "hbm_budget": "0.8 x free HBM"},
         "continuous": c, "fifo": f,
         "p99_ratio_fifo_over_continuous": round(f["p99_ms"] / c["p99_ms"], 3),
-        "throughput_ratio": round(c["pencils_per_s"] / f["pencils_per_s"], 3),
+        "p50_ratio_fifo_over_continuous": round(f["p50_ms"] / c["p50_ms"], 3),
+        "saturated": cap_res,
+        "throughput_ratio": round(cap_res["continuous"]["pencils_per_s"] / cap_res["fifo"]["pencils_per_s"], 3),
     }
     print(json.dumps(out))
+
+
+def bench_copy(args):
+    """A plain device-to-device copy of a known size (the calibration kernel
+    for the FETCH_SIZE / WRITE_SIZE counters: bytes counted per byte moved)."""
+    import torch
+    nbytes = args.copy_bytes
+    n = nbytes // 8
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / max(args.steps, 1)
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": round(2 * n * 8 / t / 1e9, 1),
+                      "unit": "GB/s", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                      "steps": args.steps, "warmup": args.warmup, "n_gpus": 1}))
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/pmc_traffic.json), if it was taken on the current source of the
+    kernel; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    h = hashlib.sha256()
+    for src in k.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != k.get("sources_sha256"):
+        return None
+    return k.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -268,8 +329,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batched", "serving"), default="single",
-                    help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch")
+    ap.add_argument("--workload", choices=("single", "batched", "serving", "copy"), default="single",
+                    help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch; "
+                         "serving: the complex128 request loop; copy: counter calibration")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--count", type=int, default=2048, help="batched: number of pencils")
     args = ap.parse_args()
 
@@ -282,6 +345,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "copy":
+        return bench_copy(args)
 
     import numpy as np
     import torch
@@ -347,7 +412,7 @@ def main():
         mean_s = ktime[dom] / klaunch[dom] * 1e-3
         achieved = per_launch_b / mean_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "kernel": dom,
                     "algorithmic_bytes_per_launch": per_launch_b,
                     "algorithmic_flops_per_launch": per_launch_f,
                     "achieved_tflops": round(per_launch_f / mean_s / 1e12, 3),
@@ -366,7 +431,7 @@ def main():
         per_launch_f = rq * K / max(klaunch[dom], 1)
         achieved = per_launch_f / mean_s / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": None, "kernel": dom,
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": measured_traffic(dom), "kernel": dom,
                     "algorithmic_flops_per_launch": per_launch_f,
                     "mean_launch_ms": round(mean_s * 1e3, 4), "launches": klaunch[dom]}
     roofline["by_kernel_ms"] = {kn: round(v, 2) for kn, v in ktime.items()}

@@ -274,6 +274,57 @@ def bench_serving(args):
     print(json.dumps(out))
 
 
+def bench_stage1(args):
+    """Stage one alone (ht_rhess / ht_rhess_z): a dense pencil with i.i.d.
+    N(0,1) (complex: CN(0,1)) entries reduced to r-HT form with Q and Z
+    accumulated.  Flops: the QR of B (about (4/3 + 2 + 4/3) n^3 with the
+    application to A and the forming of Q) plus (28p+14)/(3(p-1)) n^3 for the
+    panels, times 4 for complex."""
+    import numpy as np
+    import torch
+    import paper_2301_07964_amd as ht
+    from paper_2301_07964_amd import inputs
+    n, r, cplx = args.n, args.r, args.complex
+    A, B = inputs.dense_pencil(n, seed=args.seed, complex_=cplx)
+    A0, B0 = ht.colmajor(A), ht.colmajor(B)
+    del A, B
+    eye = torch.eye(n, dtype=A0.dtype, device=A0.device)
+    p = ht.rhess_default_p(n, r)
+    times = []
+    for it in range(args.warmup + args.steps):
+        Ad, Bd = A0.clone(), B0.clone()
+        Qd = eye.t().contiguous().t().clone()
+        Zd = Qd.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ht.rhess(Ad, Bd, r, Qd, Zd)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            times.append(time.perf_counter() - t0)
+        print(f"[bench] stage one step {it + 1}/{args.warmup + args.steps}: {time.perf_counter() - t0:.3f} s",
+              file=sys.stderr, flush=True)
+    t = sum(times) / len(times)
+    flops = ((4.0 / 3.0 + 2.0 + 4.0 / 3.0) + (28 * p + 14) / (3.0 * (p - 1))) * float(n) ** 3 * (4 if cplx else 1)
+    nb = min(r, n - 1)
+    check = None
+    if not args.no_check:
+        I = torch.eye(n, dtype=A0.dtype, device=A0.device)
+        ii = torch.arange(n, device=A0.device)
+        check = {"pattern_A": bool((Ad.abs() * (ii[:, None] > ii[None, :] + nb)).max().item() == 0),
+                 "pattern_B": bool((Bd.abs() * (ii[:, None] > ii[None, :])).max().item() == 0),
+                 "orth_Q": torch.linalg.norm(Qd.conj().t() @ Qd - I).item(),
+                 "backward_A": (torch.linalg.norm(Qd @ Ad @ Zd.conj().t() - A0) / torch.linalg.norm(A0)).item(),
+                 "backward_B": (torch.linalg.norm(Qd @ Bd @ Zd.conj().t() - B0) / torch.linalg.norm(B0)).item()}
+    print(json.dumps({"metric": "stage-one (dense -> r-HT) GFLOP/s", "value": round(flops / t / 1e9, 2),
+                      "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(t * 1e3, 2), "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "c128" if cplx else "f64", "data": "synthetic",
+                      "config": {"workload": f"stage one of a dense {'complex128' if cplx else 'FP64'} pencil, n={n}, "
+                                             f"r={r} (p={p}), Q and Z accumulated, seed {args.seed}",
+                                 "n": n, "r": r, "p": p},
+                      "flops_per_step": flops, "check": check}))
+
+
 def bench_copy(args):
     """A plain device-to-device copy of a known size (the calibration kernel
     for the FETCH_SIZE / WRITE_SIZE counters: bytes counted per byte moved)."""
@@ -329,9 +380,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batched", "serving", "copy"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "serving", "stage1", "copy"), default="single",
                     help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch; "
-                         "serving: the complex128 request loop; copy: counter calibration")
+                         "serving: the complex128 request loop; stage1: dense -> r-HT; copy: counter calibration")
+    ap.add_argument("--complex", action="store_true", help="stage1: complex128 pencil")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--count", type=int, default=2048, help="batched: number of pencils")
     args = ap.parse_args()
@@ -347,6 +399,8 @@ def main():
         return bench_serving(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "stage1":
+        return bench_stage1(args)
 
     import numpy as np
     import torch

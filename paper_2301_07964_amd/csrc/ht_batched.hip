@@ -155,11 +155,11 @@ __global__ __launch_bounds__(kBatThreads) void k_stage2_persistent(const Pencil<
                         const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
                         const S yp = bcast(y, p);
                         if (!iszero(yp)) {
-                            const double aa = sqrt(abs2(yp));
+                            const double ra = 1.0 / sqrt(abs2(yp));
                             if (im(yp) == 0.0) {
                                 if (re(yp) < 0.0) y = mk<S>(-re(y), -im(y));
                             } else {
-                                const S ph = mk<S>(re(yp) / aa, -im(yp) / aa);
+                                const S ph = mk<S>(re(yp) * ra, -im(yp) * ra);
                                 y = mul(y, ph);
                                 if (lane == p) y = mk<S>(re(y), 0.0);
                             }

@@ -52,6 +52,24 @@ __host__ __device__ inline zd recip(zd z) {
     double e = c / d, f = d + c * e; return mk<zd>(e / f, -1.0 / f);
 }
 
+// xLARFG scalars for a non-trivial reflector (ss = ||x||^2 > 0 or alpha not
+// real): beta = -sign(Re alpha) sqrt(|alpha|^2 + ss), tau = (beta - alpha) /
+// beta and sc = 1 / (alpha - beta), with a single division: 1 / beta and
+// 1 / |alpha - beta|^2 both come from q = 1 / (beta |alpha - beta|^2).
+// |Re(alpha - beta)| = |Re alpha| + |beta| >= |beta| > 0, so q is finite.
+template <class S>
+__device__ __forceinline__ void larfg_core(S alpha, double ss, S &tau, double &beta, S &sc)
+{
+    const double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
+    const S amb = sub(alpha, mk<S>(b, 0.0));
+    const double n2 = abs2(amb);
+    const double q = 1.0 / (b * n2);
+    const double rb = n2 * q;                     // 1 / beta
+    tau = mk<S>((b - re(alpha)) * rb, -im(alpha) * rb);
+    sc = scal(conj_(amb), b * q);                 // conj(amb) / |amb|^2
+    beta = b;
+}
+
 // ------------------------------------------------------- wave reductions
 // Cross-lane data movement with DPP (in-row permutations, no LDS round trip)
 // and v_readlane (broadcast of one lane into scalar registers).

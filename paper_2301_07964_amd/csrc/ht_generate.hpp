@@ -70,10 +70,10 @@ __device__ inline void wave_larfg(S x, int lane, int m, S &v, S &tau, S &beta) {
         v = (lane == 0) ? one<S>() : x;
         return;
     }
-    double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
-    tau = mk<S>((b - re(alpha)) / b, -im(alpha) / b);
+    double b;
+    S sc;
+    larfg_core(alpha, ss, tau, b, sc);
     beta = mk<S>(b, 0.0);
-    S sc = recip(sub(alpha, beta));
     v = (lane == 0) ? one<S>() : mul(x, sc);
 }
 
@@ -111,9 +111,9 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
         const S alpha = b[i];
         const double ss = (s0 + s1) + (s2 + s3);
         if (ss == 0.0 && im(alpha) == 0.0) continue;              // tau = 0: identity
-        const double bb = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
-        const S tau = mk<S>((bb - re(alpha)) / bb, -im(alpha) / bb);
-        const S sc = recip(sub(alpha, mk<S>(bb, 0.0)));          // u_c = b_c sc (c < i), u_i = 1
+        S tau, sc;                                               // u_c = b_c sc (c < i), u_i = 1
+        double bb;
+        larfg_core(alpha, ss, tau, bb, sc);
         // s = (x_i + sum_{c<i} x_c u_c) tau;  x_c -= s conj(u_c) = (s conj(sc)) conj(b_c)
         const S sv = mul(add(x[i], mul(add(p0, p1), sc)), tau);
         const S t = mul(sv, conj_(sc));
@@ -321,11 +321,11 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
                 const S yp = bcast(y, p);
                 if (!iszero(yp)) {
-                    const double aa = sqrt(abs2(yp));
+                    const double ra = 1.0 / sqrt(abs2(yp));
                     if (im(yp) == 0.0) {
                         if (re(yp) < 0.0) y = mk<S>(-re(y), -im(y));
                     } else {
-                        S ph = mk<S>(re(yp) / aa, -im(yp) / aa);
+                        S ph = mk<S>(re(yp) * ra, -im(yp) * ra);
                         y = mul(y, ph);
                         if (lane == p) y = mk<S>(re(y), 0.0);
                     }

@@ -53,11 +53,9 @@ __device__ inline void larfg_scalars(S alpha, double ss, S &tau, S &beta, S &sca
 {
     trivial = (ss == 0.0 && im(alpha) == 0.0);
     if (trivial) { tau = zero<S>(); beta = alpha; scal = one<S>(); return; }
-    const double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
-    const double rb = 1.0 / b;
-    tau = mk<S>((b - re(alpha)) * rb, -im(alpha) * rb);
+    double b;
+    larfg_core(alpha, ss, tau, b, scal);
     beta = mk<S>(b, 0.0);
-    scal = recip(sub(alpha, beta));
 }
 
 // Geometry of the chain of blocks of one panel (0-based rows).

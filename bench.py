@@ -83,7 +83,7 @@ def cpu_baseline(H, T, r, target_s=15.0):
     t0 = time.perf_counter()
     _, _, _, _, f1 = O.stage2(H, T, r, jmax=1)
     t1 = time.perf_counter() - t0
-    s = max(1, min(H.shape[0] - 2, int(target_s / max(t1, 1e-3))))
+    s = max(1, min(H.shape[0] - 2, int(round(target_s / max(t1, 1e-3)))))
     t0 = time.perf_counter()
     _, _, _, _, fs = O.stage2(H, T, r, jmax=s)
     ts = time.perf_counter() - t0
@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--r", type=int, default=32)
     ap.add_argument("--q", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--workload", choices=("single", "batched", "serving", "stage1", "copy"), default="single",

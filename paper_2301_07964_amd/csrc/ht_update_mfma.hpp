@@ -507,3 +507,118 @@ __global__ __launch_bounds__(256) void k_update_mfma_z_left(UpdArgs<zd> a, const
 }
 
 }  // namespace ht
+
+namespace ht {
+
+// Left updates, real, with LDS-staged column tiles (as for the complex kernel
+// above): one tile of 16 columns per wavefront.
+template <int P>
+__device__ __forceinline__ void tile_in_d(double *tile, int LT, const double *X, int64_t ld, int64_t n, int64_t p0,
+                                          int64_t lo, int c0, int cnt, int lane)
+{
+    constexpr int CPI = 64 / P;
+    const int rr = lane % P, jo = lane / P;
+#pragma unroll
+    for (int jj = 0; jj < 16; jj += CPI) {
+        const int j = jj + jo;
+        const int64_t col = p0 + j, row = lo + c0 + rr;
+        double v = 0.0;
+        if (rr < cnt && col < n && row < n) v = X[row + col * ld];
+        if (rr < cnt) tile[j * LT + c0 + rr] = v;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void tile_out_d(const double *tile, int LT, double *X, int64_t ld, int64_t n, int64_t p0,
+                                           int64_t lo, int c0, int cnt, int lane)
+{
+    constexpr int CPI = 64 / P;
+    const int rr = lane % P, jo = lane / P;
+#pragma unroll
+    for (int jj = 0; jj < 16; jj += CPI) {
+        const int j = jj + jo;
+        const int64_t col = p0 + j, row = lo + c0 + rr;
+        if (rr < cnt && col < n && row < n) X[row + col * ld] = tile[j * LT + c0 + rr];
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_update_mfma_left_staged(UpdArgs<double> a, const double *F)
+{
+    constexpr int KW = KWOf<R>::value;
+    constexpr int MB = KW / 16, KK = KW / 4, RS = R / 4, LT = KW + 1;
+    __shared__ double tiles[4 * 16 * LT];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double *tile = tiles + wv * 16 * LT;            // column j, window index c at tile[j*LT + c]
+    int64_t b = (int64_t)blockIdx.x * 4 + wv;
+    int jid = 0;
+    while (jid < a.njobs - 1 && b >= a.job[jid].npanels) { b -= a.job[jid].npanels; ++jid; }
+    UpdJob<double> J = a.job[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
+    if (b >= J.npanels) return;
+    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax;
+    const int64_t W = q + R - 1;
+    const int g = lane >> 4, li = lane & 15;
+    const int64_t p0 = b * 16;
+    double *X = J.X;
+    const int64_t ld = J.ld;
+
+    int64_t kfirst = kmax - 1;
+    if (J.lim >= 0) {
+        while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
+        if (kfirst < 0) return;
+    }
+    double xb[KK];
+    tile_in_d<KW>(tile, LT, X, ld, n, p0, j1 + kfirst * R, 0, (int)W, lane);
+    lds_wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+        const int c = 4 * kk + g;
+        xb[kk] = c < W ? tile[li * LT + c] : 0.0;
+    }
+    for (int64_t k = kfirst; k >= 0; --k) {
+        const int64_t lo = j1 + k * R;
+        const double *Fk = F + k * (KW * KW);
+        f64x4 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            double af[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) af[mb] = Fk[(mb * KK + kk) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], xb[kk], acc[mb], 0, 0, 0);
+        }
+        const int f0 = (k == 0) ? 0 : (int)(q - 1);
+        lds_wave_sync();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * mb + 4 * v + g;
+                if (c >= f0 && c < W) tile[li * LT + c] = acc[mb][v];
+            }
+        lds_wave_sync();
+        if (k == 0) {
+            tile_out_d<KW>(tile, LT, X, ld, n, p0, lo, 0, (int)W, lane);
+            break;
+        }
+        tile_out_d<R>(tile, LT, X, ld, n, p0, lo, f0, (int)(W - f0), lane);
+        const int64_t lon = lo - R;
+#pragma unroll
+        for (int kk = 0; kk < RS; ++kk) {
+            const int c = 4 * kk + g;
+            xb[kk + RS] = (c < q - 1) ? acc[kk >> 2][kk & 3] : 0.0;
+        }
+        lds_wave_sync();
+        tile_in_d<R>(tile, LT, X, ld, n, p0, lon, 0, R, lane);
+        lds_wave_sync();
+#pragma unroll
+        for (int kk = 0; kk < RS; ++kk) xb[kk] = tile[li * LT + 4 * kk + g];
+    }
+}
+
+}  // namespace ht

@@ -146,3 +146,61 @@ def test_batched_invalid_arguments():
     with pytest.raises(ht.HTError) as e:                 # min(r, n-1) = 34 > 32
         ht.stage2_batched([(H40, H40.clone(), None, None, 34)])
     assert e.value.code == 4
+
+
+def test_back_to_back_batches_on_one_stream():
+    """Two batched calls enqueued on one stream without a host synchronisation
+    in between (the second reuses the stream's pinned descriptor buffer while
+    the first may still run) give the same results as the calls made apart."""
+    ht = _ht()
+    a = _sample(40, 21)
+    b = _sample(17, 22)
+    ref_a = _run_batched(a)
+    ref_b = _run_batched(b)
+    st = torch.cuda.Stream()
+    da, db = _device_pencils(a), _device_pencils(b)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        ht.stage2_batched(da, stream=st)
+        ht.stage2_batched(db, stream=st)
+    st.synchronize()
+    for dev, ref in ((da, ref_a), (db, ref_b)):
+        for p, r in zip(dev, ref):
+            for x, y in zip(p[:4], r):
+                assert np.array_equal(ht.to_numpy(x), y)
+
+
+def test_reserved_workspace_serves_later_calls():
+    """ht_reserve_workspace sizes a stream's workspace once; stage-two and
+    stage-one calls on that stream then run (and match the default stream's
+    results bit for bit)."""
+    ht = _ht()
+    n, r = 300, 16
+    st = torch.cuda.Stream()
+    need = max(ht.workspace_bytes(n, r, 0, True), ht.rhess_workspace_bytes(n, r, 0, True))
+    ht.reserve_workspace(need, st)
+    H, T = inputs.rht_pencil_complex(n, r, 5)
+    outs = []
+    for stream in (st, None):
+        Hd, Td = ht.colmajor(H), ht.colmajor(T)
+        Qd = ht.colmajor(np.eye(n, dtype=H.dtype))
+        Zd = ht.colmajor(np.eye(n, dtype=H.dtype))
+        torch.cuda.synchronize()
+        if stream is None:
+            ht.stage2(Hd, Td, r, Qd, Zd)
+        else:
+            with torch.cuda.stream(stream):
+                ht.stage2(Hd, Td, r, Qd, Zd, stream=stream)
+        torch.cuda.synchronize()
+        outs.append([ht.to_numpy(x) for x in (Hd, Td, Qd, Zd)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    A, B = inputs.dense_pencil(n, seed=6, complex_=True)
+    Ad, Bd = ht.colmajor(A), ht.colmajor(B)
+    with torch.cuda.stream(st):
+        ht.rhess(Ad, Bd, r, stream=st)
+    st.synchronize()
+    An, Bn = ht.to_numpy(Ad), ht.to_numpy(Bd)
+    assert np.all(np.tril(An, -(r + 1)) == 0) and np.all(np.tril(Bn, -1) == 0)
+    with pytest.raises(ht.HTError):
+        ht.reserve_workspace(-1, st)

@@ -312,6 +312,19 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
     for (int64_t k = kfirst; k >= klast; --k) {
         const int64_t lo = j1 + k * R;
         const double *Fr = Fs + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
+        // the next window's new indices (lo-r .. lo-1) are not written by this
+        // window: load them now so that their latency overlaps the products
+        double nr[RS], ni[RS];
+#pragma unroll
+        for (int kk = 0; kk < RS; ++kk) {
+            const int c = 4 * kk + g;
+            bool ok;
+            const int64_t ad = addr(lo - R, c, ok);
+            zd v = zero<zd>();
+            if (ok && k > klast) v = X[ad];
+            nr[kk] = v.re;
+            ni[kk] = v.im;
+        }
         f64x4 ar[MB], ai[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) { ar[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; ai[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; }
@@ -342,7 +355,6 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
                 if (ok && c >= f0 && c < W) X[ad] = mk<zd>(ar[mb][v], ai[mb][v]);
             }
         if (k == klast) break;
-        const int64_t lon = lo - R;
 #pragma unroll
         for (int kk = 0; kk < RS; ++kk) {
             const int c = 4 * kk + g;
@@ -351,15 +363,7 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
             xi[kk + RS] = keep ? ai[kk >> 2][kk & 3] : 0.0;
         }
 #pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const int c = 4 * kk + g;
-            bool ok;
-            const int64_t ad = addr(lon, c, ok);
-            zd v = zero<zd>();
-            if (ok) v = X[ad];
-            xr[kk] = v.re;
-            xi[kk] = v.im;
-        }
+        for (int kk = 0; kk < RS; ++kk) { xr[kk] = nr[kk]; xi[kk] = ni[kk]; }
     }
 }
 

@@ -130,7 +130,7 @@ def test_invalid_arguments():
     assert ht.lib().ht_stage2_q(ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(H.data_ptr()), None, None, 8, 2, 8, 3, None) == -8
 
 
-@pytest.mark.parametrize("n,r,q", [(1100, 8, 8), (1030, 16, 16), (700, 8, 4)])
+@pytest.mark.parametrize("n,r,q", [(1100, 8, 8), (1030, 16, 16), (700, 8, 4), (900, 32, 32)])
 def test_parity_many_windows(n, r, q):
     """Regression: more than ~64 windows per group with q = r once amplified
     rounding residue left in structurally-zero entries between groups."""
@@ -159,7 +159,8 @@ def _backward(Hin, Tin, r, q=0):
     return res
 
 
-@pytest.mark.parametrize("n,r,cplx", [(2048, 8, False), (4096, 16, False), (2048, 32, True), (1500, 4, True)])
+@pytest.mark.parametrize("n,r,cplx", [(2048, 8, False), (4096, 16, False), (3000, 32, False), (2048, 32, True),
+                                      (1500, 4, True)])
 def test_backward_error_large(n, r, cplx):
     """Invariants at sizes the oracle is too slow for: exact zeros, orthogonality and
     backward error within 100 n eps (eps = 2^-52)."""

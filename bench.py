@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--r", type=int, default=32)
     ap.add_argument("--q", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--workload", choices=("single", "batched", "serving", "stage1", "copy"), default="single",

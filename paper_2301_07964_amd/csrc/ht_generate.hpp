@@ -44,7 +44,8 @@ struct GenArgs {
     S *SH, *ST;        // scratch band copies of H and T
     S *VL, *TL;        // left reflectors:  VL[((w*kext)+k)*r + i], TL[w*kext + k]
     S *VR, *TR;        // right reflectors
-    int *progress;     // per sweep of the group: number of finished blocks
+    int *progress;     // per sweep of the group: blocks whose step chain is finished
+    int *hdone;        // per sweep: blocks whose far rows (the helper workgroup's part) are finished
 };
 
 template <class S> __device__ inline S shfl_(S v, int src);
@@ -128,7 +129,7 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
 // it is written back.
 template <class S, int RM>
 __device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
-                                  const S *sw, S sig, int tid)
+                                  const S *sw, S sig, int tid, int64_t zrow = INT64_MAX)
 {
     const int64_t cs = B.ldb - 1;                  // stride between columns of one band row
     for (int64_t row = top + tid; row <= bot; row += 256) {
@@ -148,13 +149,81 @@ __device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot,
         const S sx = mul(add(d0, d1), sig);
 #pragma unroll
         for (int c = 0; c < RM; ++c)
-            if (c < m) p[c * cs] = sub(x[c], mul(sx, conj_(sw[c])));
+            if (c < m) p[c * cs] = (c == 0 && row >= zrow) ? zero<S>() : sub(x[c], mul(sx, conj_(sw[c])));
     }
+}
+
+// Helper workgroup of sweep w (the second half of the grid): the "far" part of
+// each step's eager right update, one step behind the sweep's own workgroup.
+// Step k's right reflector is applied to rows topH .. j1+(k+1)r of H and (for
+// all but the last sweep) rows topT .. i2 of T in the block's columns, with the
+// exact zeros of T's column i1 below the diagonal.  The sweep's own workgroup
+// has done the rows from j1+(k+1)r+1 on, the only ones its next steps read;
+// the successor sweep waits for both counters.
+template <class S, int RM>
+__device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
+{
+    const int tid = threadIdx.x;
+    const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
+    const int64_t j = j1 + w, d = j2 - j;
+    const int64_t nbj = nblocks(n, r, j);
+    const Band B = a.band;
+    __shared__ int s_go;
+    __shared__ S hsw[64];
+    __shared__ S hsig;
+    for (int64_t k = 0; k < kext; ++k) {
+        if (tid == 0) {
+            int polls = 0, ok = 1;
+            while (ld_acquire(a.progress + w) < (int)(k + 1)) {
+                if (++polls > (1 << 22)) { ok = 0; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_go = ok;
+        }
+        __syncthreads();
+        if (!s_go) {                                // uniform: the sweep's workgroup never finished step k
+            if (tid == 0) st_release(a.hdone + w, 0x3fffffff);
+            return;
+        }
+        if (k < nbj) {
+            const int64_t i1 = j + k * r + 1;
+            const int64_t i2 = i64min(j + (k + 1) * r, n);
+            const int m = (int)(i2 - i1 + 1);
+            if (tid < 64) hsw[tid] = tid < m ? a.VR[(w * kext + k) * r + tid] : zero<S>();
+            if (tid == 0) hsig = a.TR[w * kext + k];
+            __syncthreads();
+            const S sig = hsig;
+            const bool tdo = d >= 1 && !iszero(sig);
+            if (!iszero(sig)) {
+                const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
+                const int64_t nlo = i64max(topH, j1 + (k + 1) * r + 1);
+                right_rows<S, RM>(a.SH, B, topH, nlo - 1, i1, m, hsw, sig, tid);
+                if (tdo) {
+                    const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
+                    right_rows<S, RM>(a.ST, B, topT, i2, i1, m, hsw, sig, tid, i1 + 1);
+                }
+            }
+            if (!tdo)
+                for (int e = tid; e < m - 1; e += 256) a.ST[B.idx(i1 + e, i1 - 1)] = zero<S>();
+        }
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            st_release(a.hdone + w, (int)(k + 1));
+        }
+    }
+    __syncthreads();
+    if (tid == 0) st_release(a.hdone + w, 0x3fffffff);
 }
 
 template <class S, int RM>
 __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 {
+    if ((int64_t)blockIdx.x > a.j2 - a.j1) {       // second half of the grid: far-row helpers
+        gen_far<S, RM>(a, (int)(blockIdx.x - (a.j2 - a.j1 + 1)));
+        return;
+    }
     const int w = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
@@ -179,7 +248,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             if (tid == 0) {
                 int polls = 0;
                 s_abort = 0;
-                while (ld_acquire(a.progress + w - 1) < (int)(k + 3)) {
+                while (ld_acquire(a.progress + w - 1) < (int)(k + 3) || ld_acquire(a.hdone + w - 1) < (int)(k + 3)) {
                     if (++polls > (1 << 22)) { s_abort = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }
@@ -338,19 +407,14 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             }
             __syncthreads();
 
-            // ---- 4. eager right updates on the band
+            // ---- 4. eager right updates: the rows of H this sweep's next steps
+            // read (from j1+(k+1)r+1 on); the helper workgroup does the rest
             const S sig = stau[2];
             if (!iszero(sig)) {
                 const int64_t d = j2 - j;
                 const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
-                right_rows<S, RM>(SH, B, topH, i3, i1, m, sw, sig, tid);
-                if (d >= 1) {
-                    const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
-                    right_rows<S, RM>(ST, B, topT, i2, i1, m, sw, sig, tid);
-                }
+                right_rows<S, RM>(SH, B, i64max(topH, j1 + (k + 1) * r + 1), i3, i1, m, sw, sig, tid);
             }
-            __syncthreads();
-            for (int e = tid; e < m - 1; e += 256) ST[B.idx(i1 + e, i1 - 1)] = zero<S>();
         } else {
             // absent block: mark both reflectors as identities
             if (tid < r) {

@@ -129,7 +129,7 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
 // it is written back.
 template <class S, int RM>
 __device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
-                                  const S *sw, S sig, int tid, int64_t zrow = INT64_MAX)
+                                  const S *sw, S sig, int tid)
 {
     const int64_t cs = B.ldb - 1;                  // stride between columns of one band row
     for (int64_t row = top + tid; row <= bot; row += 256) {
@@ -149,7 +149,50 @@ __device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot,
         const S sx = mul(add(d0, d1), sig);
 #pragma unroll
         for (int c = 0; c < RM; ++c)
-            if (c < m) p[c * cs] = (c == 0 && row >= zrow) ? zero<S>() : sub(x[c], mul(sx, conj_(sw[c])));
+            if (c < m) p[c * cs] = sub(x[c], mul(sx, conj_(sw[c])));
+    }
+}
+
+// The far rows of one step in one pass: rows [topH, topH+nH) of H, then rows
+// [topT, topT+nT) of T (the first column zeroed from row zrowT on), as one
+// index space over the workgroup; each thread loads U row segments before it
+// writes any, so U rounds of loads are in flight together.
+template <class S, int RM, int U>
+__device__ __forceinline__ void far_rows(S *XH, S *XT, const Band &B, int64_t topH, int64_t nH, int64_t topT,
+                                         int64_t nT, int64_t i1, int m, const S *sw, S sig, int tid, int64_t zrowT)
+{
+    const int64_t cs = B.ldb - 1;
+    const int64_t tot = nH + nT;
+    for (int64_t e0 = tid; e0 < tot; e0 += 256 * U) {
+        S x[U][RM];
+        S *p[U];
+        bool zr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + 256 * u;
+            const bool isH = e < nH;
+            const int64_t row = isH ? topH + e : topT + (e - nH);
+            p[u] = e < tot ? (isH ? XH : XT) + B.idx(row - 1, i1 - 1) : nullptr;
+            zr[u] = !isH && row >= zrowT;
+#pragma unroll
+            for (int c = 0; c < RM; ++c) {
+                x[u][c] = zero<S>();
+                if (p[u] != nullptr && c < m) x[u][c] = p[u][c * cs];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            S d0 = zero<S>(), d1 = zero<S>();
+#pragma unroll
+            for (int c = 0; c < RM; c += 2) {
+                d0 = add(d0, mul(x[u][c], sw[c]));
+                d1 = add(d1, mul(x[u][c + 1], sw[c + 1]));
+            }
+            const S sx = mul(add(d0, d1), sig);
+#pragma unroll
+            for (int c = 0; c < RM; ++c)
+                if (p[u] != nullptr && c < m) p[u][c * cs] = (c == 0 && zr[u]) ? zero<S>() : sub(x[u][c], mul(sx, conj_(sw[c])));
+        }
     }
 }
 
@@ -198,11 +241,10 @@ __device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
             if (!iszero(sig)) {
                 const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
                 const int64_t nlo = i64max(topH, j1 + (k + 1) * r + 1);
-                right_rows<S, RM>(a.SH, B, topH, nlo - 1, i1, m, hsw, sig, tid);
-                if (tdo) {
-                    const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
-                    right_rows<S, RM>(a.ST, B, topT, i2, i1, m, hsw, sig, tid, i1 + 1);
-                }
+                const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
+                constexpr int U = sizeof(S) * RM <= 256 ? 2 : 1;     // two rows per thread while registers allow
+                far_rows<S, RM, U>(a.SH, a.ST, B, topH, nlo - topH, topT, tdo ? i2 - topT + 1 : 0, i1, m, hsw, sig,
+                                   tid, i1 + 1);
             }
             if (!tdo)
                 for (int e = tid; e < m - 1; e += 256) a.ST[B.idx(i1 + e, i1 - 1)] = zero<S>();

@@ -215,14 +215,16 @@ static int launch_update(bool right, const UpdArgs<S> &ua, int64_t panels, hipSt
 template <int R>
 static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, hipStream_t st)
 {
-    if (left && R == 32 && ua.n < 12288) {
-        // left updates at r = 32: LDS-staged column tiles, one tile of 16 per wavefront (measured:
-        // 224 ms against 283 ms at n = 8192; at n = 16384 two direct tiles per wavefront win, 1470 ms
-        // against 1752 ms)
-        int64_t tot = 0;
-        for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + 15) / 16; tot += ua.job[i].npanels; }
-        hipLaunchKernelGGL((k_update_mfma_left_staged<R>), dim3((unsigned)((tot + 3) / 4)), dim3(256), 0, st, ua, F);
-        return launch_check("k_update_mfma_left_staged");
+    if constexpr (R == 32) {
+        if (left) {
+            // left updates at r = 32: one tile of 16 columns per workgroup, the window's product split
+            // over its four wavefronts (measured: n = 8192 87 ms against 224 ms for one LDS-staged tile
+            // per wavefront; n = 16384 1120 ms against 1463 ms for two direct tiles per wavefront)
+            int64_t tot = 0;
+            for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + 15) / 16; tot += ua.job[i].npanels; }
+            hipLaunchKernelGGL((k_update_mfma_coop<R, true, 1>), dim3((unsigned)tot), dim3(256), 0, st, ua, F);
+            return launch_check("k_update_mfma_coop(left)");
+        }
     }
     const int trw = ua.n >= 8192 ? 2 : 1;
     const int64_t tile = 16 * trw;

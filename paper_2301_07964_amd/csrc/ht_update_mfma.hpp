@@ -514,114 +514,144 @@ __global__ __launch_bounds__(256) void k_update_mfma_z_left(UpdArgs<zd> a, const
 
 namespace ht {
 
-// Left updates, real, with LDS-staged column tiles (as for the complex kernel
-// above): one tile of 16 columns per wavefront.
-template <int P>
-__device__ __forceinline__ void tile_in_d(double *tile, int LT, const double *X, int64_t ld, int64_t n, int64_t p0,
-                                          int64_t lo, int c0, int cnt, int lane)
+// Delayed updates, real, r = 32, one tile of NL = 16 TC rows (right) or
+// columns (left) per workgroup.  The four wavefronts split each window's
+// product by output index (wavefront v forms indices 16v .. 16v+15 of the
+// window for all NL lines, with its quarter of the factor), so a tile's
+// sequence of windows advances at a quarter of the matrix-core time per
+// window and each factor fragment serves TC line blocks.  The tile's window
+// lives in LDS (the current window and the next); finished indices leave
+// through a staging buffer with stores that run along the contiguous
+// dimension; the next window's new indices and factor fragments are loaded
+// before the current window's products.  Tiles with the longest sequences of
+// windows (top rows for right updates, rightmost columns for left updates)
+// are dispatched first, jobs interleaved.  The library launches the left form
+// with TC = 1; TC = 2, and the right form for H and T (faster by itself, but
+// then overlapping the Q, Z update on the other stream), were no faster over a
+// whole reduction.
+template <int R, bool LEFT, int TC>
+__global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, const double *F)
 {
-    constexpr int CPI = 64 / P;
-    const int rr = lane % P, jo = lane / P;
-#pragma unroll
-    for (int jj = 0; jj < 16; jj += CPI) {
-        const int j = jj + jo;
-        const int64_t col = p0 + j, row = lo + c0 + rr;
-        double v = 0.0;
-        if (rr < cnt && col < n && row < n) v = X[row + col * ld];
-        if (rr < cnt) tile[j * LT + c0 + rr] = v;
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void tile_out_d(const double *tile, int LT, double *X, int64_t ld, int64_t n, int64_t p0,
-                                           int64_t lo, int c0, int cnt, int lane)
-{
-    constexpr int CPI = 64 / P;
-    const int rr = lane % P, jo = lane / P;
-#pragma unroll
-    for (int jj = 0; jj < 16; jj += CPI) {
-        const int j = jj + jo;
-        const int64_t col = p0 + j, row = lo + c0 + rr;
-        if (rr < cnt && col < n && row < n) X[row + col * ld] = tile[j * LT + c0 + rr];
-    }
-}
-
-template <int R>
-__global__ __launch_bounds__(256) void k_update_mfma_left_staged(UpdArgs<double> a, const double *F)
-{
-    constexpr int KW = KWOf<R>::value;
-    constexpr int MB = KW / 16, KK = KW / 4, RS = R / 4, LT = KW + 1;
-    __shared__ double tiles[4 * 16 * LT];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double *tile = tiles + wv * 16 * LT;            // column j, window index c at tile[j*LT + c]
-    int64_t b = (int64_t)blockIdx.x * 4 + wv;
-    int jid = 0;
-    while (jid < a.njobs - 1 && b >= a.job[jid].npanels) { b -= a.job[jid].npanels; ++jid; }
+    static_assert(R == 32, "one 16-index block of the window factor per wavefront");
+    constexpr int KW = KWOf<R>::value, KK = KW / 4, LT = KW + 1, NL = 16 * TC;
+    __shared__ double buf[2][NL * LT];             // tile line j, window index c at [j*LT + c]
+    __shared__ double ob[2][NL * LT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int jid = (int)(blockIdx.x % a.njobs);
     UpdJob<double> J = a.job[0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
-    if (b >= J.npanels) return;
-    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax;
-    const int64_t W = q + R - 1;
+    const int64_t bi = (int64_t)(blockIdx.x / a.njobs);
+    const int64_t b = LEFT ? J.npanels - 1 - bi : bi;
+    if (b < 0 || b >= J.npanels) return;
+    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
+    const int W = (int)(q + R - 1);
     const int g = lane >> 4, li = lane & 15;
-    const int64_t p0 = b * 16;
+    const int64_t p0 = b * NL;
+    const double *Fs = F + (LEFT ? 0 : (int64_t)J.side * kext * (KW * KW));
     double *X = J.X;
     const int64_t ld = J.ld;
 
-    int64_t kfirst = kmax - 1;
+    int64_t kfirst = kmax - 1, klast = 0;
     if (J.lim >= 0) {
-        while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
-        if (kfirst < 0) return;
-    }
-    double xb[KK];
-    tile_in_d<KW>(tile, LT, X, ld, n, p0, j1 + kfirst * R, 0, (int)W, lane);
-    lds_wave_sync();
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-        const int c = 4 * kk + g;
-        xb[kk] = c < W ? tile[li * LT + c] : 0.0;
-    }
-    for (int64_t k = kfirst; k >= 0; --k) {
-        const int64_t lo = j1 + k * R;
-        const double *Fk = F + k * (KW * KW);
-        f64x4 acc[MB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            double af[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) af[mb] = Fk[(mb * KK + kk) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], xb[kk], acc[mb], 0, 0, 0);
+        if (!LEFT) {
+            while (klast < kmax && !(p0 < i64min(j1 + klast * R + W - 1, n - 1) + 1 + J.lim)) ++klast;
+            if (klast >= kmax) return;
+        } else {
+            while (kfirst >= 0 && !(p0 + NL > j1 + kfirst * R - J.lim)) --kfirst;
+            if (kfirst < 0) return;
         }
-        const int f0 = (k == 0) ? 0 : (int)(q - 1);
-        lds_wave_sync();
+    }
+    // element (tile line j, window index c) of the window starting at lo
+    auto at = [&](int j, int64_t lo, int c, bool &ok) -> int64_t {
+        const int64_t fixed = p0 + j, idx = lo + c;
+        ok = fixed < n && idx < n;
+        return LEFT ? idx + fixed * ld : fixed + idx * ld;
+    };
+    // element e of a whole window (NL x 64) or of the new indices (NL x R),
+    // the contiguous dimension fastest
+    auto wmap = [&](int e, int &j, int &c) { if (LEFT) { c = e & 63; j = e >> 6; } else { j = e % NL; c = e / NL; } };
+    auto nmap = [&](int e, int &j, int &c) { if (LEFT) { c = e % R; j = e / R; } else { j = e % NL; c = e / NL; } };
+    {
+        const int64_t lo = j1 + kfirst * R;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int i = 0; i < 4 * TC; ++i) {
+            int j, c;
+            wmap(tid + 256 * i, j, c);
+            bool ok;
+            const int64_t ad = at(j, lo, c, ok);
+            buf[0][j * LT + c] = (ok && c < W) ? X[ad] : 0.0;
+            buf[1][j * LT + c] = 0.0;              // indices >= W of the other buffer stay zero
+        }
+    }
+    double pre[2 * TC];
+    auto load_new = [&](int64_t kn) {
+        const int64_t lo = j1 + kn * R;
+#pragma unroll
+        for (int i = 0; i < 2 * TC; ++i) {
+            int j, c;
+            nmap(tid + 256 * i, j, c);
+            bool ok;
+            const int64_t ad = at(j, lo, c, ok);
+            pre[i] = ok ? X[ad] : 0.0;
+        }
+    };
+    if (kfirst > klast) load_new(kfirst - 1);
+    double af[KK];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) af[kk] = Fs[kfirst * (KW * KW) + (wv * KK + kk) * 64 + lane];
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k = kfirst; k >= klast; --k) {
+        const int64_t lo = j1 + k * R;
+        const bool more = k > klast;
+        double afn[KK];
+        if (more) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) afn[kk] = Fs[(k - 1) * (KW * KW) + (wv * KK + kk) * 64 + lane];
+        }
+        f64x4 acc[TC];
+#pragma unroll
+        for (int t = 0; t < TC; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+            for (int t = 0; t < TC; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], buf[cur][(16 * t + li) * LT + 4 * kk + g], acc[t],
+                                                              0, 0, 0);
+        const int f0 = more ? (int)(q - 1) : 0;
+        const int nxt = cur ^ 1;
+        double *ow = ob[k & 1];
+#pragma unroll
+        for (int t = 0; t < TC; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int c = 16 * mb + 4 * v + g;
-                if (c >= f0 && c < W) tile[li * LT + c] = acc[mb][v];
+                const int c = 16 * wv + 4 * v + g, j = 16 * t + li;
+                if (c >= f0 && c < W) ow[j * LT + c] = acc[t][v];
+                if (more && c < q - 1) buf[nxt][j * LT + c + R] = acc[t][v];    // index c + R of window k-1
             }
-        lds_wave_sync();
-        if (k == 0) {
-            tile_out_d<KW>(tile, LT, X, ld, n, p0, lo, 0, (int)W, lane);
-            break;
-        }
-        tile_out_d<R>(tile, LT, X, ld, n, p0, lo, f0, (int)(W - f0), lane);
-        const int64_t lon = lo - R;
+        if (more) {
 #pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const int c = 4 * kk + g;
-            xb[kk + RS] = (c < q - 1) ? acc[kk >> 2][kk & 3] : 0.0;
+            for (int i = 0; i < 2 * TC; ++i) {
+                int j, c;
+                nmap(tid + 256 * i, j, c);
+                buf[nxt][j * LT + c] = pre[i];
+            }
         }
-        lds_wave_sync();
-        tile_in_d<R>(tile, LT, X, ld, n, p0, lon, 0, R, lane);
-        lds_wave_sync();
+        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < RS; ++kk) xb[kk] = tile[li * LT + 4 * kk + g];
+        for (int i = 0; i < 4 * TC; ++i) {
+            int j, c;
+            wmap(tid + 256 * i, j, c);
+            bool ok;
+            const int64_t ad = at(j, lo, c, ok);
+            if (ok && c >= f0 && c < W) X[ad] = ow[j * LT + c];
+        }
+        if (!more) break;
+        if (k - 1 > klast) load_new(k - 2);
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) af[kk] = afn[kk];
+        cur = nxt;
     }
 }
 

@@ -252,17 +252,23 @@ static int launch_update_mfma(bool left, const UpdArgs<double> &ua, const double
     }
 }
 
-// Complex matrix-core application kernels (one tile of 16 per wavefront).
+// Complex matrix-core application kernels (tiles of 16 rows / columns).
 template <int R>
 static int launch_update_mfma_z_r(bool left, UpdArgs<zd> ua, const double *F, hipStream_t st)
 {
     int64_t tot = 0;
     for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + 15) / 16; tot += ua.job[i].npanels; }
     const dim3 grid((unsigned)((tot + 3) / 4)), blk(256);
-    // left updates: the LDS-staged kernel at r = 32 (measured 1.8x faster at n = 8192); at r <= 16 the
-    // direct loads are faster (their tiles are narrower and more of them are resident)
-    if (left && R == 32) hipLaunchKernelGGL((k_update_mfma_z_left<R>), grid, blk, 0, st, ua, F);
-    else if (left) hipLaunchKernelGGL((k_update_mfma_z<R, true>), grid, blk, 0, st, ua, F);
+    // left updates at r = 32: one column tile per workgroup, the window product split over its four
+    // wavefronts (n = 8192: 613 ms against 800 ms for one LDS-staged tile per wavefront, 1.63 s for
+    // direct loads); at r <= 16 the direct loads are faster (narrower tiles, more of them resident)
+    if constexpr (R == 32) {
+        if (left) {
+            hipLaunchKernelGGL((k_update_mfma_z_coop_left<R>), dim3((unsigned)tot), blk, 0, st, ua, F);
+            return launch_check("k_update_mfma_z_coop_left");
+        }
+    }
+    if (left) hipLaunchKernelGGL((k_update_mfma_z<R, true>), grid, blk, 0, st, ua, F);
     else hipLaunchKernelGGL((k_update_mfma_z<R, false>), grid, blk, 0, st, ua, F);
     return launch_check(left ? "k_update_mfma_z(left)" : "k_update_mfma_z(right)");
 }

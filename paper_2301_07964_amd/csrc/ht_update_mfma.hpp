@@ -371,149 +371,6 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
 
 namespace ht {
 
-// Left updates, complex, with the column tiles staged through LDS.  In the
-// MFMA operand layout a load instruction of the left update touches 16
-// columns x 4 rows (64-byte pieces); here every wavefront moves its window
-// rows of its 16 columns between HBM and a private LDS tile with loads and
-// stores whose lanes run down a column (P consecutive rows per column, 64/P
-// columns per instruction), and takes the operands from the tile.
-template <int P>
-__device__ __forceinline__ void tile_in(zd *tile, int LT, const zd *X, int64_t ld, int64_t n, int64_t p0,
-                                        int64_t lo, int c0, int cnt, int lane)
-{
-    constexpr int CPI = 64 / P;
-    const int rr = lane % P, jo = lane / P;
-#pragma unroll
-    for (int jj = 0; jj < 16; jj += CPI) {
-        const int j = jj + jo;
-        const int64_t col = p0 + j, row = lo + c0 + rr;
-        zd v = zero<zd>();
-        if (rr < cnt && col < n && row < n) v = X[row + col * ld];
-        if (rr < cnt) tile[j * LT + c0 + rr] = v;
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void tile_out(const zd *tile, int LT, zd *X, int64_t ld, int64_t n, int64_t p0,
-                                         int64_t lo, int c0, int cnt, int lane)
-{
-    constexpr int CPI = 64 / P;
-    const int rr = lane % P, jo = lane / P;
-#pragma unroll
-    for (int jj = 0; jj < 16; jj += CPI) {
-        const int j = jj + jo;
-        const int64_t col = p0 + j, row = lo + c0 + rr;
-        if (rr < cnt && col < n && row < n) X[row + col * ld] = tile[j * LT + c0 + rr];
-    }
-}
-
-__device__ __forceinline__ void lds_wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int R>
-__global__ __launch_bounds__(256) void k_update_mfma_z_left(UpdArgs<zd> a, const double *F)
-{
-    constexpr int KW = KWOf<R>::value;
-    constexpr int MB = KW / 16, KK = KW / 4, RS = R / 4, LT = KW + 1;
-    __shared__ zd tiles[4 * 16 * LT];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    zd *tile = tiles + wv * 16 * LT;                // column j, window index c at tile[j*LT + c]
-    int64_t b = (int64_t)blockIdx.x * 4 + wv;
-    int jid = 0;
-    while (jid < a.njobs - 1 && b >= a.job[jid].npanels) { b -= a.job[jid].npanels; ++jid; }
-    UpdJob<zd> J = a.job[0];
-#pragma unroll
-    for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
-    if (b >= J.npanels) return;
-    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax;
-    const int64_t W = q + R - 1;
-    const int g = lane >> 4, li = lane & 15;
-    const int64_t p0 = b * 16;                      // first column of the tile
-    zd *X = J.X;
-    const int64_t ld = J.ld;
-
-    int64_t kfirst = kmax - 1;
-    if (J.lim >= 0) {
-        while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
-        if (kfirst < 0) return;
-    }
-    double xr[KK], xi[KK];
-    tile_in<KW>(tile, LT, X, ld, n, p0, j1 + kfirst * R, 0, (int)W, lane);
-    lds_wave_sync();
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-        const int c = 4 * kk + g;
-        const zd v = c < W ? tile[li * LT + c] : zero<zd>();
-        xr[kk] = v.re;
-        xi[kk] = v.im;
-    }
-    for (int64_t k = kfirst; k >= 0; --k) {
-        const int64_t lo = j1 + k * R;
-        const double *Fr = F + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
-        f64x4 ar[MB], ai[MB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) { ar[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; ai[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; }
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            double fr[MB], fi[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                fr[mb] = Fr[(mb * KK + kk) * 64 + lane];
-                fi[mb] = -Fi[(mb * KK + kk) * 64 + lane];      // U^H: conjugate
-            }
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xr[kk], ar[mb], 0, 0, 0);
-                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[mb], xi[kk], ar[mb], 0, 0, 0);
-                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xi[kk], ai[mb], 0, 0, 0);
-                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[mb], xr[kk], ai[mb], 0, 0, 0);
-            }
-        }
-        // finished window indices f0 .. W-1 back to HBM through the tile
-        const int f0 = (k == 0) ? 0 : (int)(q - 1);
-        lds_wave_sync();                            // earlier reads of the tile are done
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = 16 * mb + 4 * v + g;
-                if (c >= f0 && c < W) tile[li * LT + c] = mk<zd>(ar[mb][v], ai[mb][v]);
-            }
-        lds_wave_sync();
-        if (k == 0) {
-            tile_out<KW>(tile, LT, X, ld, n, p0, lo, 0, (int)W, lane);
-            break;
-        }
-        tile_out<R>(tile, LT, X, ld, n, p0, lo, f0, (int)(W - f0), lane);
-        // carry local 0 .. q-2 to local r .. W-1 of window k-1, load its new indices 0 .. r-1
-        const int64_t lon = lo - R;
-#pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const int c = 4 * kk + g;
-            const bool keep = c < q - 1;
-            xr[kk + RS] = keep ? ar[kk >> 2][kk & 3] : 0.0;
-            xi[kk + RS] = keep ? ai[kk >> 2][kk & 3] : 0.0;
-        }
-        lds_wave_sync();                            // the stores have read the tile
-        tile_in<R>(tile, LT, X, ld, n, p0, lon, 0, R, lane);
-        lds_wave_sync();
-#pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const zd v = tile[li * LT + 4 * kk + g];
-            xr[kk] = v.re;
-            xi[kk] = v.im;
-        }
-    }
-}
-
-}  // namespace ht
-
-namespace ht {
-
 // Delayed updates, real, r = 32, one tile of NL = 16 TC rows (right) or
 // columns (left) per workgroup.  The four wavefronts split each window's
 // product by output index (wavefront v forms indices 16v .. 16v+15 of the
@@ -651,6 +508,115 @@ __global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, con
         if (k - 1 > klast) load_new(k - 2);
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) af[kk] = afn[kk];
+        cur = nxt;
+    }
+}
+
+// Left updates, complex, r = 32: the four-wavefront tile scheme of
+// k_update_mfma_coop (left form, TC = 1) for complex data (four real products
+// per complex one, A = U^H).  One finished-row staging buffer, so two
+// barriers per window.
+template <int R>
+__global__ __launch_bounds__(256) void k_update_mfma_z_coop_left(UpdArgs<zd> a, const double *F)
+{
+    static_assert(R == 32, "one 16-index block of the window factor per wavefront");
+    constexpr int KW = KWOf<R>::value, KK = KW / 4, LT = KW + 1;
+    __shared__ zd buf[2][16 * LT];                 // column j, window index c at [j*LT + c]
+    __shared__ zd ob[16 * LT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int jid = (int)(blockIdx.x % a.njobs);
+    UpdJob<zd> J = a.job[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
+    const int64_t b = J.npanels - 1 - (int64_t)(blockIdx.x / a.njobs);   // rightmost tiles first
+    if (b < 0) return;
+    const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax;
+    const int W = (int)(q + R - 1);
+    const int g = lane >> 4, li = lane & 15;
+    const int64_t p0 = b * 16;
+    zd *X = J.X;
+    const int64_t ld = J.ld;
+
+    int64_t kfirst = kmax - 1;
+    if (J.lim >= 0) {
+        while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
+        if (kfirst < 0) return;
+    }
+    // whole window: row tid % 64 of columns tid / 64 + 4i; new rows: row
+    // tid % 32 of columns tid / 32 + 8i
+    const int wr = tid & 63, wc = tid >> 6, nr = tid & 31, nc = tid >> 5;
+    {
+        const int64_t lo = j1 + kfirst * R;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = wc + 4 * i;
+            const int64_t col = p0 + j, row = lo + wr;
+            zd v = zero<zd>();
+            if (wr < W && col < n && row < n) v = X[row + col * ld];
+            buf[0][j * LT + wr] = v;
+            buf[1][j * LT + wr] = zero<zd>();      // indices >= W of the other buffer stay zero
+        }
+    }
+    zd pre[2];
+    auto load_new = [&](int64_t kn) {
+        const int64_t lo = j1 + kn * R;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t col = p0 + nc + 8 * i, row = lo + nr;
+            pre[i] = (col < n && row < n) ? X[row + col * ld] : zero<zd>();
+        }
+    };
+    if (kfirst > 0) load_new(kfirst - 1);
+    double fr[KK], fi[KK];
+    auto load_f = [&](int64_t k, double (&r_)[KK], double (&i_)[KK]) {
+        const double *Fr = F + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            r_[kk] = Fr[(wv * KK + kk) * 64 + lane];
+            i_[kk] = -Fi[(wv * KK + kk) * 64 + lane];          // U^H: conjugate
+        }
+    };
+    load_f(kfirst, fr, fi);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k = kfirst; k >= 0; --k) {
+        const int64_t lo = j1 + k * R;
+        double frn[KK], fin[KK];
+        if (k > 0) load_f(k - 1, frn, fin);
+        f64x4 ar = f64x4{0.0, 0.0, 0.0, 0.0}, ai = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const zd v = buf[cur][li * LT + 4 * kk + g];
+            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.re, ar, 0, 0, 0);
+            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[kk], v.im, ar, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.im, ai, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[kk], v.re, ai, 0, 0, 0);
+        }
+        const int f0 = (k == 0) ? 0 : (int)(q - 1);
+        const int nxt = cur ^ 1;
+        __syncthreads();                            // the previous window's stores have read ob
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = 16 * wv + 4 * v + g;
+            const zd z = mk<zd>(ar[v], ai[v]);
+            if (c >= f0 && c < W) ob[li * LT + c] = z;
+            if (k > 0 && c < q - 1) buf[nxt][li * LT + c + R] = z;   // index c + R of window k-1
+        }
+        if (k > 0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) buf[nxt][(nc + 8 * i) * LT + nr] = pre[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = wc + 4 * i;
+            const int64_t col = p0 + j, row = lo + wr;
+            if (wr >= f0 && wr < W && col < n && row < n) X[row + col * ld] = ob[j * LT + wr];
+        }
+        if (k == 0) break;
+        if (k > 1) load_new(k - 2);
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) { fr[kk] = frn[kk]; fi[kk] = fin[kk]; }
         cur = nxt;
     }
 }

@@ -283,14 +283,19 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 
     for (int64_t k = 0; k < kext; ++k) {
         if (w > 0) {
-            // bounded wait: a predecessor step takes microseconds; after ~2^22
+            // step k of this sweep follows steps 0..k+2 of the previous sweep
+            // (the last of them writes the column this step's near rows
+            // update) and that sweep's far rows of steps 0..k+1 (step k+1's
+            // reach this step's T block, its lazy T column and its near rows;
+            // step k+2's lie right of every column this step touches).
+            // Bounded wait: a predecessor step takes microseconds; after ~2^22
             // polls the workgroup gives up (the output is then invalid) so that
             // no wave can spin forever
             __shared__ int s_abort;
             if (tid == 0) {
                 int polls = 0;
                 s_abort = 0;
-                while (ld_acquire(a.progress + w - 1) < (int)(k + 3) || ld_acquire(a.hdone + w - 1) < (int)(k + 3)) {
+                while (ld_acquire(a.progress + w - 1) < (int)(k + 3) || ld_acquire(a.hdone + w - 1) < (int)(k + 2)) {
                     if (++polls > (1 << 22)) { s_abort = 1; break; }
                     __builtin_amdgcn_s_sleep(1);
                 }

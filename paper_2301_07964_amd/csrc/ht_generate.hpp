@@ -125,31 +125,37 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
 }
 
 // rows [top, bot] (1-based) of the band copy X, columns i1 .. i1+m-1:
-// X <- X (I - sig w w^H); each row segment is loaded completely before any of
-// it is written back.
+// X <- X (I - sig w w^H), four lanes per row (each with RM/4 columns of it, the
+// dot product summed over the four), 64 rows per pass of the workgroup; a
+// row's entries are all loaded before any of them is written back.
 template <class S, int RM>
-__device__ inline void right_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
-                                  const S *sw, S sig, int tid)
+__device__ inline void near_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
+                                 const S *sw, S sig, int tid)
 {
+    constexpr int CP = RM / 4;                     // columns per lane
     const int64_t cs = B.ldb - 1;                  // stride between columns of one band row
-    for (int64_t row = top + tid; row <= bot; row += 256) {
+    const int part = tid & 3, lane = tid & 63;
+    for (int64_t r0 = top; r0 <= bot; r0 += 64) {
+        const int64_t row = r0 + (tid >> 2);
+        const bool on = row <= bot;
         S *p = X + B.idx(row - 1, i1 - 1);
-        S x[RM];
+        S x[CP];
+        S ds = zero<S>();
 #pragma unroll
-        for (int c = 0; c < RM; ++c) {
+        for (int c = 0; c < CP; ++c) {
+            const int cc = part * CP + c;
             x[c] = zero<S>();
-            if (c < m) x[c] = p[c * cs];
+            if (on && cc < m) x[c] = p[cc * cs];
+            ds = add(ds, mul(x[c], sw[cc]));
         }
-        S d0 = zero<S>(), d1 = zero<S>();
+        ds = add(ds, shfl_(ds, lane ^ 1));         // every lane takes part in the exchange
+        ds = add(ds, shfl_(ds, lane ^ 2));
+        const S sx = mul(ds, sig);
 #pragma unroll
-        for (int c = 0; c < RM; c += 2) {
-            d0 = add(d0, mul(x[c], sw[c]));
-            d1 = add(d1, mul(x[c + 1], sw[c + 1]));
+        for (int c = 0; c < CP; ++c) {
+            const int cc = part * CP + c;
+            if (on && cc < m) p[cc * cs] = sub(x[c], mul(sx, conj_(sw[cc])));
         }
-        const S sx = mul(add(d0, d1), sig);
-#pragma unroll
-        for (int c = 0; c < RM; ++c)
-            if (c < m) p[c * cs] = sub(x[c], mul(sx, conj_(sw[c])));
     }
 }
 
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             if (!iszero(sig)) {
                 const int64_t d = j2 - j;
                 const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
-                right_rows<S, RM>(SH, B, i64max(topH, j1 + (k + 1) * r + 1), i3, i1, m, sw, sig, tid);
+                near_rows<S, RM>(SH, B, i64max(topH, j1 + (k + 1) * r + 1), i3, i1, m, sw, sig, tid);
             }
         } else {
             // absent block: mark both reflectors as identities

@@ -128,9 +128,10 @@ def unblocked_key(t):
     return (w, k, 0 if kind == "c" else 1)
 
 
-def violations(n, r, q, chain_lag=3, helper_lag=2):
-    tasks, kext = tasks_of_group(n, r, 1, min(q, n - 2))
-    qq = min(q, n - 2)
+def violations(n, r, q, chain_lag=3, helper_lag=2, j1=1):
+    j2 = min(j1 + q - 1, n - 2)
+    qq = j2 - j1 + 1
+    tasks, kext = tasks_of_group(n, r, j1, j2)
     reach = happens_before(tasks, edges(qq, kext, chain_lag, helper_lag))
     touch = {}
     for t, (rd, wr) in tasks.items():
@@ -150,6 +151,12 @@ def violations(n, r, q, chain_lag=3, helper_lag=2):
 @pytest.mark.parametrize("n,r,q", [(40, 3, 4), (61, 4, 4), (70, 4, 2), (90, 8, 8), (75, 5, 3), (50, 2, 6)])
 def test_generation_schedule_is_race_free(n, r, q):
     assert violations(n, r, q) == set()
+
+
+@pytest.mark.parametrize("n,r,q,j1", [(61, 4, 4, 5), (61, 4, 4, 45), (90, 8, 8, 41), (50, 3, 3, 44)])
+def test_later_groups_are_race_free(n, r, q, j1):
+    # groups further down, including a last group shorter than q
+    assert violations(n, r, q, j1=j1) == set()
 
 
 def test_model_detects_a_missing_wait():

@@ -4,9 +4,10 @@
 Default workload: one real FP64 r-Hessenberg-triangular pencil, n = 16384,
 r = 32, seed 0, Q and Z accumulated (the configuration the headline metric is
 quoted on).  A step is one full stage-two reduction ``ht_stage2`` of one
-pencil.  All inputs of the timed steps are resident in HBM before the timed
-region starts (one fresh copy per step, prepared beforehand); the timed region
-covers exactly ``--steps`` reductions bracketed by device synchronisation.
+pencil.  The inputs of every step are restored in HBM from pristine device
+copies before the step (outside the timed region); the timed region is the sum
+over exactly ``--steps`` reductions, each bracketed by device
+synchronisation.
 
 Prints ONE JSON line: the metric (counted-flop GFLOP/s, see below), the
 roofline record of the dominant kernel (measured live with HIP events on the
@@ -32,41 +33,51 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 HBM_PEAK_GBS = 8000.0
 
 
-def generate_bytes(n, r, q, esz=8):
-    """Algorithmic HBM bytes of the generate phase over a whole reduction: per
-    step (sweep j of a group j1..j2, d = j2 - j, full block k) the eager right
-    updates read and write rows topH..i3 of H and (d >= 1) topT..i2 of T in the
-    block's m columns, with topH = max(j1+1, j1+1+(k+1-d) r) and topT =
-    max(j1+1, j1+1+(k-d) r); plus the T block (m x m) and the reduced column of
-    H (m entries), also read and written.  1-based indices as in the paper."""
+def generate_band_bytes(n, r, q, esz=8):
+    """Algorithmic HBM bytes of the generate phase, per group (list over the
+    groups): the band of H and T that the generate phase of Section 3.2 updates,
+    each entry read and written once per group.  Ranges of the right reflector
+    of step (j, k) (the generate algorithm of the appendix, with the top rows
+    derived for the grouped order, d = j2 - j): rows
+    max(j1+1, j1+1+(k+1-d) r) .. min(j+(k+2)r, n) of H and
+    max(j1+1, j1+1+(k-d) r) .. min(j+(k+1)r, n) of T in the block's columns.
+    Per column the band is the union of the row ranges of the steps whose
+    block holds it.  1-based indices as in the paper."""
     import numpy as np
-    tot = 0.0
+    out = []
+    c = np.arange(1, n + 1, dtype=np.int64)          # 1-based columns
     for j1 in range(1, n - 1, q):
         j2 = min(j1 + q - 1, n - 2)
+        topH = np.full(n, n + 1, dtype=np.int64)
+        topT = np.full(n, n + 1, dtype=np.int64)
+        botH = np.zeros(n, dtype=np.int64)
+        botT = np.zeros(n, dtype=np.int64)
         for j in range(j1, j2 + 1):
             if n - j - 2 < 0:
                 continue
             nb = 1 + (n - j - 2) // r
             d = j2 - j
-            k = np.arange(nb, dtype=np.int64)
-            i1 = j + k * r + 1
+            k = (c - j - 1) // r                         # block of sweep j holding column c
+            on = (c >= j + 1) & (k < nb)
             i2 = np.minimum(j + (k + 1) * r, n)
             i3 = np.minimum(j + (k + 2) * r, n)
-            m = (i2 - i1 + 1).astype(np.float64)
-            top_h = np.maximum(j1 + 1, j1 + 1 + (k + 1 - d) * r)
-            rows = (i3 - top_h + 1).astype(np.float64)
-            if d >= 1:
-                top_t = np.maximum(j1 + 1, j1 + 1 + (k - d) * r)
-                rows += (i2 - top_t + 1).astype(np.float64)
-            tot += float(np.sum((rows * m + m * m + m) * 2 * esz))
-    return tot
+            tH = np.maximum(j1 + 1, j1 + 1 + (k + 1 - d) * r)
+            tT = np.maximum(j1 + 1, j1 + 1 + (k - d) * r)
+            topH = np.where(on, np.minimum(topH, tH), topH)
+            topT = np.where(on, np.minimum(topT, tT), topT)
+            botH = np.where(on, np.maximum(botH, i3), botH)
+            botT = np.where(on, np.maximum(botT, i2), botT)
+        rows = np.where(botH > 0, botH - topH + 1, 0) + np.where(botT > 0, botT - topT + 1, 0)
+        out.append(float(rows.sum()) * 2 * esz)
+    return out
 
 
 def counted_flops_by_class(n, r):
     """Algorithmic flops of the unblocked algorithm, split by the kernel class
     of the blocked implementation that performs them: right updates of H and T
     (rows 1..i3 of H, 1..i2 of T), updates of Q and Z (all n rows each) and
-    left updates of H and T (columns jb+1..n of H, i1..n of T)."""
+    left updates of H and T (columns jb..n of H, i1..n of T, the ranges the
+    algorithm states)."""
     import numpy as np
     right = qz = left = 0.0
     for j in range(1, n - 1):
@@ -79,7 +90,7 @@ def counted_flops_by_class(n, r):
         m = (i2 - i1 + 1).astype(np.float64)
         right += float(np.sum(4.0 * m * (i3 + i2)))
         qz += float(np.sum(4.0 * m * 2.0 * n))
-        left += float(np.sum(4.0 * m * ((n - jb) + (n - i1 + 1))))
+        left += float(np.sum(4.0 * m * ((n - jb + 1) + (n - i1 + 1))))
     return {"update_right": right, "update_qz": qz, "update_left": left}
 
 
@@ -106,19 +117,46 @@ def update_bytes_by_class(n, r, q):
     return {"update_right": 16.0 * right, "update_qz": 16.0 * qz, "update_left": 16.0 * left}
 
 
-def cpu_baseline(H, T, r, target_s=15.0):
-    """The oracle on the host: the first s sweeps of the same pencil."""
-    import numpy as np
+def update_mfma_flops_by_class(n, r, q):
+    """Flops the matrix-core application kernels execute: every line (row for
+    right updates, column for left updates) a window reaches is multiplied by
+    the window's dense orthogonal factor of order KW = max(16, 2r), 2 KW^2
+    flops, with the line ranges of update_bytes_by_class."""
+    KW = max(16, 2 * r)
+    right = qz = left = 0.0
+    for j1 in range(1, n - 1, q):
+        kmax = 1 + (n - j1 - 2) // r
+        W = min(q, n - 1 - j1) + r - 1
+        for k in range(kmax):
+            lo = j1 + k * r
+            hi = min(lo + W - 1, n - 1)
+            right += min(n, hi + 1 + (q + 2) * r) + min(n, hi + 1 + (q + 1) * r)
+            qz += 2 * n
+            left += 2 * (n - max(0, lo - (q + 1) * r))
+    f = 2.0 * KW * KW
+    return {"update_right": f * right, "update_qz": f * qz, "update_left": f * left}
+
+
+def cpu_baseline(H, T, r, target_s=20.0):
+    """The oracle on the host cores (its threaded form, bitwise equal to one
+    thread): the first s sweeps of the same pencil, s sized from a timed first
+    sweep for about target_s seconds of work."""
     from oracle import oracle as O
-    t0 = time.perf_counter()
-    _, _, _, _, f1 = O.stage2(H, T, r, jmax=1)
-    t1 = time.perf_counter() - t0
-    s = max(1, min(H.shape[0] - 2, int(round(target_s / max(t1, 1e-3)))))
-    t0 = time.perf_counter()
-    _, _, _, _, fs = O.stage2(H, T, r, jmax=s)
-    ts = time.perf_counter() - t0
-    return {"value": round(fs / ts / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {s} of {H.shape[0] - 2} sweeps of the same pencil (counted flops {fs:.3e}, {ts:.1f} s, 1 thread)"}
+    cores = max(1, min(O.host_cores(), 64))
+    old = O.set_threads(cores)
+    try:
+        t0 = time.perf_counter()
+        _, _, _, _, f1 = O.stage2(H, T, r, jmax=1)
+        t1 = time.perf_counter() - t0
+        s = max(1, min(H.shape[0] - 2, int(target_s / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        _, _, _, _, fs = O.stage2(H, T, r, jmax=s)
+        ts = time.perf_counter() - t0
+    finally:
+        O.set_threads(old)
+    return {"value": round(fs / ts / 1e9, 4), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {s} of {H.shape[0] - 2} sweeps of the same pencil (counted flops {fs:.3e}, "
+                      f"{ts:.1f} s including the copy-in of H, T and the identity Q, Z; {cores} threads)"}
 
 
 def bench_batched(args):
@@ -410,6 +448,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--lookahead", type=int, default=None, choices=(0, 1),
+                    help="overlap generation with the previous group's updates (library knob); default: the library's")
     ap.add_argument("--workload", choices=("single", "batched", "serving", "stage1", "copy"), default="single",
                     help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch; "
                          "serving: the complex128 request loop; stage1: dense -> r-HT; copy: counter calibration")
@@ -445,31 +485,41 @@ def main():
     H, T = inputs.rht_pencil(n, r, args.seed)
     Hd0, Td0 = ht.colmajor(H, dev), ht.colmajor(T, dev)
     q = args.q if args.q else ht.default_q(n, r)
-    copies = []
-    for _ in range(W + K):
-        Hd = Hd0.clone(memory_format=torch.preserve_format)
-        Td = Td0.clone(memory_format=torch.preserve_format)
-        Qd = torch.eye(n, dtype=torch.float64, device=dev).t()
-        Zd = torch.eye(n, dtype=torch.float64, device=dev).t()
-        copies.append((Hd, Td, Qd, Zd))
-    torch.cuda.synchronize()
+    if args.lookahead is not None:
+        ht.set_knob(ht.KNOB_LOOKAHEAD, args.lookahead)
+    # one working set, restored from the pristine copies before every step
+    # (outside the timed region)
+    Hd, Td = torch.empty_like(Hd0), torch.empty_like(Td0)
+    Qd = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
+    Zd = torch.empty_strided((n, n), (1, n), dtype=torch.float64, device=dev)
+
+    def restore():
+        Hd.copy_(Hd0)
+        Td.copy_(Td0)
+        for X in (Qd, Zd):
+            X.zero_()
+            X.diagonal().fill_(1.0)
+        torch.cuda.synchronize()
+
     stream = torch.cuda.current_stream()
     for i in range(W):
         print(f"[bench] warmup {i + 1}/{W}", file=sys.stderr, flush=True)
-        Hd, Td, Qd, Zd = copies[i]
+        restore()
         ht.stage2(Hd, Td, r, Qd, Zd, q=q, stream=stream)
         torch.cuda.synchronize()
 
     ht.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    elapsed = 0.0
     for i in range(K):
-        Hd, Td, Qd, Zd = copies[W + i]
+        restore()
+        t0 = time.perf_counter()
         ht.stage2(Hd, Td, r, Qd, Zd, q=q, stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        print(f"[bench] step {i + 1}/{K}: {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
     ht.profile_enable(False)
     prof = ht.profile_read()
+    status = ht.stream_status(stream)
     print(f"[bench] {K} steps in {elapsed:.3f} s; kernel ms: "
           + ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items()), file=sys.stderr, flush=True)
 
@@ -477,11 +527,13 @@ def main():
     total_flops = sum(per_class_flops.values())
     value = total_flops * K / elapsed / 1e9
 
-    # roofline of the dominant kernel class (algorithmic flops per launch / mean launch time)
-    # roofline of the dominant kernel (by total time over the timed region);
-    # the application kernels stream every entry they update once per group
-    # (q/4 flop per byte, below the FP64 ridge 78.6/8 = 9.8): HBM bound
+    # Roofline of the dominant kernel (by total time over the timed region).
+    # The application kernels stream every entry they update once per group
+    # (about q/4 algorithmic flop per byte, below the FP64 ridge 78.6/8 = 9.8):
+    # HBM bound.  Generation is a latency-bound pipeline; its algorithmic bytes
+    # are the band it updates, read and written once per group.
     per_class_bytes = update_bytes_by_class(n, r, q)
+    per_class_exec = update_mfma_flops_by_class(n, r, q)
     mfma = r in (4, 8, 16, 32)
     kernels = {("k_update_mfma<right>" if mfma else "k_update_right_reg<double>"): ("update_right", "update_qz"),
                ("k_update_mfma<left>" if mfma else "k_update_left_reg<double>"): ("update_left",),
@@ -489,45 +541,44 @@ def main():
     ktime = {kn: sum(prof[c][0] for c in cl) for kn, cl in kernels.items()}
     klaunch = {kn: sum(prof[c][1] for c in cl) for kn, cl in kernels.items()}
     dom = max(ktime, key=ktime.get)
+    updates = {}
+    for kn, cl in kernels.items():
+        if kn == "k_generate<double>" or klaunch[kn] == 0:
+            continue
+        mean_s = ktime[kn] / klaunch[kn] * 1e-3
+        b = sum(per_class_bytes[c] for c in cl) * K / klaunch[kn]
+        f = sum(per_class_flops[c] for c in cl) * K / klaunch[kn]
+        fx = sum(per_class_exec[c] for c in cl) * K / klaunch[kn]
+        updates[kn] = {"mean_launch_ms": round(mean_s * 1e3, 4), "launches": klaunch[kn],
+                       "hbm_gbs": round(b / mean_s / 1e9, 1), "hbm_frac": round(b / mean_s / 1e9 / HBM_PEAK_GBS, 4),
+                       "algorithmic_tflops": round(f / mean_s / 1e12, 3),
+                       "mfma_executed_tflops": round(fx / mean_s / 1e12, 3) if mfma else None,
+                       "mfma_frac": round(fx / mean_s / 1e12 / FP64_PEAK_TFLOPS, 4) if mfma else None,
+                       "traffic": measured_traffic(kn)}
     if dom != "k_generate<double>" and klaunch[dom] > 0:
-        # FP64 matrix-core and vector peaks are equal on MI355X (78.6 TFLOP/s)
+        u = updates[dom]
         per_launch_b = sum(per_class_bytes[c] for c in kernels[dom]) * K / klaunch[dom]
-        per_launch_f = sum(per_class_flops[c] for c in kernels[dom]) * K / klaunch[dom]
-        mean_s = ktime[dom] / klaunch[dom] * 1e-3
-        achieved = per_launch_b / mean_s / 1e9
+        achieved = per_launch_b / (u["mean_launch_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "kernel": dom,
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": u["traffic"], "kernel": dom,
                     "algorithmic_bytes_per_launch": per_launch_b,
-                    "algorithmic_flops_per_launch": per_launch_f,
-                    "achieved_tflops": round(per_launch_f / mean_s / 1e12, 3),
-                    "mean_launch_ms": round(mean_s * 1e3, 4), "launches": klaunch[dom]}
+                    "mean_launch_ms": u["mean_launch_ms"], "launches": klaunch[dom]}
     else:
-        # generation: the eager right updates of the scratch band (rows topH..i3
-        # of H, topT..i2 of T in the block's columns, read and written once per
-        # step) are the bytes it must move; reported against HBM, with the flops
-        # of its RQ factorisations of [T block; I] ((10/3) m^3 per step) beside
-        per_launch_b = generate_bytes(n, r, q) * K / max(klaunch[dom], 1)
-        import numpy as np
-        rq = 0.0
-        for j in range(1, n - 1):
-            nb = 1 + (n - j - 2) // r
-            k = np.arange(nb, dtype=np.int64)
-            m = (np.minimum(j + (k + 1) * r, n) - (j + k * r + 1) + 1).astype(np.float64)
-            rq += float(np.sum(10.0 / 3.0 * m ** 3))
-        mean_s = ktime[dom] / max(klaunch[dom], 1) * 1e-3
-        per_launch_f = rq * K / max(klaunch[dom], 1)
+        band = generate_band_bytes(n, r, q)
+        launches = max(klaunch[dom], 1)
+        per_launch_b = sum(band) * K / launches
+        mean_s = ktime[dom] / launches * 1e-3
         achieved = per_launch_b / mean_s / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "kernel": dom,
+        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured_traffic(dom), "kernel": dom,
                     "algorithmic_bytes_per_launch": per_launch_b,
-                    "algorithmic_flops_per_launch": per_launch_f,
-                    "achieved_tflops": round(per_launch_f / mean_s / 1e12, 4),
+                    "algorithmic_bytes": "the band of H and T the generate phase updates, read and written once "
+                                         "per group (mean over the groups)",
                     "mean_launch_ms": round(mean_s * 1e3, 4), "launches": klaunch[dom]}
     roofline["by_kernel_ms"] = {kn: round(v, 2) for kn, v in ktime.items()}
 
     check = None
     if not args.no_check:
-        Hd, Td, Qd, Zd = copies[-1]
         eps = float(np.finfo(np.float64).eps)
         Hr = torch.tril(Hd, -2).abs().max().item() if n > 2 else 0.0
         Tr = torch.tril(Td, -1).abs().max().item() if n > 1 else 0.0
@@ -539,7 +590,8 @@ def main():
         bound = 100 * n * eps
         check = {"exact_zeros": Hr == 0.0 and Tr == 0.0, "orth_Q": orth_q, "orth_Z": orth_z,
                  "backward_H": bH, "backward_T": bT, "bound_100neps": bound,
-                 "ok": Hr == 0.0 and Tr == 0.0 and max(orth_q, orth_z, bH, bT) <= bound}
+                 "device_status": status,
+                 "ok": status == 0 and Hr == 0.0 and Tr == 0.0 and max(orth_q, orth_z, bH, bT) <= bound}
         del I
 
     cpu = None
@@ -567,6 +619,7 @@ def main():
         "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
         "kernel_launches": {k: v[1] for k, v in prof.items()},
         "roofline": roofline,
+        "update_kernels": updates,
         "cpu_baseline": cpu,
         "check": check,
     }

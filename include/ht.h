@@ -42,6 +42,7 @@ extern "C" {
 #define HT_ERR_NOMEM 2   /* device workspace allocation failed */
 #define HT_ERR_LAUNCH 3  /* a kernel launch failed */
 #define HT_ERR_NOTSUP 4  /* configuration not supported by this build */
+#define HT_ERR_TIMEOUT 5 /* a bounded device-side wait gave up (ht_stream_status) */
 
 /*
  * ht_stage2 -- reduce an r-Hessenberg-triangular pencil to Hessenberg-
@@ -81,6 +82,54 @@ int ht_stage2_q(double *H, double *T, double *Q, double *Z,
                 int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
 int ht_stage2_z_q(void *H, void *T, void *Q, void *Z,
                   int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
+
+/*
+ * ht_stage2_sweeps -- the first jmax sweeps of stage two only (sweeps
+ * j = 1..jmax of the unblocked algorithm, Section 3.1; jmax < 0 or
+ * jmax >= n-2 means all of them, i.e. ht_stage2_q).  The sweeps are run in
+ * groups of q as ht_stage2_q does, the last group cut at jmax.  On exit
+ * columns 1..jmax of H are reduced (exact zeros below the first subdiagonal),
+ * the rest of (H, T) holds the band structure the unblocked algorithm leaves
+ * after sweep jmax (its structural zeros written as exact zeros), and Q, Z
+ * are accumulated as for ht_stage2.  The final exact-zero pass of a complete
+ * reduction is not run when jmax < n-2.  Meant for checking a long reduction
+ * one prefix at a time, and for callers that reduce a pencil in pieces.
+ * Errors as ht_stage2_q.
+ */
+int ht_stage2_sweeps(double *H, double *T, double *Q, double *Z, int64_t n,
+                     int64_t r, int64_t ld, int64_t q, int64_t jmax,
+                     void *stream);
+int ht_stage2_z_sweeps(void *H, void *T, void *Q, void *Z, int64_t n,
+                       int64_t r, int64_t ld, int64_t q, int64_t jmax,
+                       void *stream);
+
+/*
+ * ht_stream_status -- device-side failures of the calls enqueued on `stream`
+ * since the last query.  The generate kernel of stage two coordinates its
+ * workgroups with bounded waits on device counters (Section 3.2's pipeline of
+ * sweeps); a wait that gives up sets a bit in a per-(device, stream) status
+ * word and every workgroup then exits normally, with the output of that call
+ * invalid.  This call waits for `stream`, reads and clears that word, and
+ * returns 0 (no failure), HT_ERR_TIMEOUT, or HT_ERR_HIP / HT_ERR_NOMEM.
+ */
+int ht_stream_status(void *stream);
+
+/*
+ * Process-wide knobs (defaults in brackets).  ht_set_knob returns 0, -1 for an
+ * unknown knob or -2 for a value out of range; ht_get_knob returns the value
+ * or -1 for an unknown knob.  Calls already enqueued are not affected.
+ *   HT_KNOB_WAIT_POLLS [2^22]: polls before a device-side wait gives up; 0
+ *     makes every wait give up at once (used to test the failure path).
+ *   HT_KNOB_UPDATE_TILE_ROWS [0]: tiles of 16 rows per wavefront in the
+ *     matrix-core right updates; 0 = automatic (2 for n >= 8192), 1 or 2.
+ *   HT_KNOB_LOOKAHEAD [0]: 1 = overlap the generation of each group of sweeps
+ *     with the delayed updates of the previous group (Section 3.3).
+ */
+#define HT_KNOB_WAIT_POLLS 1
+#define HT_KNOB_UPDATE_TILE_ROWS 2
+#define HT_KNOB_LOOKAHEAD 3
+int ht_set_knob(int knob, int64_t value);
+int64_t ht_get_knob(int knob);
 
 /*
  * ht_stage2_batched -- `count` independent stage-two reductions (pencils of

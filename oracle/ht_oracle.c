@@ -26,6 +26,12 @@
  *     up to a unimodular scalar, so its direction y is normalised to make the
  *     first nonzero entry real and positive before xLARFG is applied to it.
  *   - Entries annihilated by a reflector are written as exact zeros.
+ *
+ * Threads: oracle_set_threads(t) lets the reflector applications split their
+ * independent columns (left updates) or rows (right updates) over t OpenMP
+ * threads.  Every entry then sees exactly the operation sequence of the
+ * one-thread run, so the results are bitwise equal for any t (a test checks
+ * this); the default is one thread.
  */
 #include <math.h>
 #include <stdint.h>
@@ -33,6 +39,18 @@
 #include <string.h>
 
 typedef struct { double re, im; } zdbl;
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 1;
+/* minimum number of independent vectors before a reflector application is
+ * split over threads */
+#define PAR_MIN 512
+
+void oracle_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+int oracle_get_threads(void) { return g_threads; }
 
 /* ---------- explicit complex arithmetic (no reliance on C complex rules) -- */
 static zdbl zmk(double re, double im) { zdbl z; z.re = re; z.im = im; return z; }
@@ -194,6 +212,7 @@ static void left_d(double *X, int64_t ld, int64_t a, int64_t m, int64_t c0, int6
                    const double *v, double tau)
 {
     if (tau == 0.0) return;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && c1 - c0 + 1 >= PAR_MIN)
     for (int64_t c = c0; c <= c1; ++c) {
         double *col = X + a + c * ld;
         double s = 0.0;
@@ -209,14 +228,19 @@ static void right_d(double *X, int64_t ld, int64_t a, int64_t m, int64_t r0, int
     if (tau == 0.0 || r1 < r0) return;
     int64_t nr = r1 - r0 + 1;
     double *s = (double *)calloc((size_t)nr, sizeof(double));
-    for (int64_t j = 0; j < m; ++j) {
-        const double *col = X + r0 + (a + j) * ld;
-        for (int64_t i = 0; i < nr; ++i) s[i] += col[i] * v[j];
-    }
-    for (int64_t j = 0; j < m; ++j) {
-        double *col = X + r0 + (a + j) * ld;
-        double tv = tau * v[j];
-        for (int64_t i = 0; i < nr; ++i) col[i] -= s[i] * tv;
+    /* rows are independent: each chunk of rows runs the same column loops */
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && nr >= PAR_MIN)
+    for (int64_t i0 = 0; i0 < nr; i0 += 256) {
+        int64_t ie = i0 + 256 < nr ? i0 + 256 : nr;
+        for (int64_t j = 0; j < m; ++j) {
+            const double *col = X + r0 + (a + j) * ld;
+            for (int64_t i = i0; i < ie; ++i) s[i] += col[i] * v[j];
+        }
+        for (int64_t j = 0; j < m; ++j) {
+            double *col = X + r0 + (a + j) * ld;
+            double tv = tau * v[j];
+            for (int64_t i = i0; i < ie; ++i) col[i] -= s[i] * tv;
+        }
     }
     free(s);
 }
@@ -226,6 +250,7 @@ static void left_z(zdbl *X, int64_t ld, int64_t a, int64_t m, int64_t c0, int64_
 {
     if (tau.re == 0.0 && tau.im == 0.0) return;
     zdbl ct = zconj(tau);
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && c1 - c0 + 1 >= PAR_MIN)
     for (int64_t c = c0; c <= c1; ++c) {
         zdbl *col = X + a + c * ld;
         zdbl s = zmk(0.0, 0.0);
@@ -241,14 +266,18 @@ static void right_z(zdbl *X, int64_t ld, int64_t a, int64_t m, int64_t r0, int64
     if ((tau.re == 0.0 && tau.im == 0.0) || r1 < r0) return;
     int64_t nr = r1 - r0 + 1;
     zdbl *s = (zdbl *)calloc((size_t)nr, sizeof(zdbl));
-    for (int64_t j = 0; j < m; ++j) {
-        const zdbl *col = X + r0 + (a + j) * ld;
-        for (int64_t i = 0; i < nr; ++i) s[i] = zadd(s[i], zmul(col[i], v[j]));
-    }
-    for (int64_t j = 0; j < m; ++j) {
-        zdbl *col = X + r0 + (a + j) * ld;
-        zdbl tv = zmul(tau, zconj(v[j]));
-        for (int64_t i = 0; i < nr; ++i) col[i] = zsub(col[i], zmul(s[i], tv));
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1 && nr >= PAR_MIN)
+    for (int64_t i0 = 0; i0 < nr; i0 += 256) {
+        int64_t ie = i0 + 256 < nr ? i0 + 256 : nr;
+        for (int64_t j = 0; j < m; ++j) {
+            const zdbl *col = X + r0 + (a + j) * ld;
+            for (int64_t i = i0; i < ie; ++i) s[i] = zadd(s[i], zmul(col[i], v[j]));
+        }
+        for (int64_t j = 0; j < m; ++j) {
+            zdbl *col = X + r0 + (a + j) * ld;
+            zdbl tv = zmul(tau, zconj(v[j]));
+            for (int64_t i = i0; i < ie; ++i) col[i] = zsub(col[i], zmul(s[i], tv));
+        }
     }
     free(s);
 }
@@ -260,7 +289,9 @@ static void right_z(zdbl *X, int64_t ld, int64_t a, int64_t m, int64_t r0, int64
 /*   i1 = j+kr+1, i2 = min(j+(k+1)r,n), i3 = min(j+(k+2)r,n).                */
 /* Runs sweeps 1..jmax (jmax < 0: all).  Q, Z may be NULL.  Adds the number  */
 /* of counted flops (4 * reflector length * vectors updated per reflector    */
-/* application; complex x4) to *flops when flops != NULL.                    */
+/* application over the ranges the algorithm states, the left reflector on   */
+/* H(i1:i2, jb:n) including the column it reduces; complex x4) to *flops     */
+/* when flops != NULL.                                                       */
 /* Entries outside the r-HT pattern are not read: they are overwritten by 0. */
 /* ------------------------------------------------------------------------ */
 static void zero_outside_d(int64_t n, int64_t r, double *H, double *T, int64_t ld)
@@ -324,7 +355,7 @@ int oracle_stage2_d(int64_t n, int64_t r, double *H, double *T, double *Q, doubl
             for (int64_t i = 1; i < m; ++i) H[a + i + cb * ld] = 0.0;
             left_d(H, ld, a, m, cb + 1, n - 1, v, tau);          /* H <- G^H H */
             left_d(T, ld, a, m, a, n - 1, v, tau);               /* T <- G^H T */
-            fl += 4.0 * m * (double)(n - jb) + 4.0 * m * (double)(n - i1 + 1);
+            fl += 4.0 * m * (double)(n - jb + 1) + 4.0 * m * (double)(n - i1 + 1);
             if (Q) { right_d(Q, ld, a, m, 0, n - 1, v, tau); fl += 4.0 * m * n; }   /* Q <- Q G */
             /* opposite reflector from the RQ factorisation of T(i1:i2, i1:i2) */
             for (int64_t c = 0; c < m; ++c)
@@ -377,7 +408,7 @@ int oracle_stage2_z(int64_t n, int64_t r, zdbl *H, zdbl *T, zdbl *Q, zdbl *Z,
             for (int64_t i = 1; i < m; ++i) H[a + i + cb * ld] = zmk(0.0, 0.0);
             left_z(H, ld, a, m, cb + 1, n - 1, v, tau);
             left_z(T, ld, a, m, a, n - 1, v, tau);
-            fl += 16.0 * m * (double)(n - jb) + 16.0 * m * (double)(n - i1 + 1);
+            fl += 16.0 * m * (double)(n - jb + 1) + 16.0 * m * (double)(n - i1 + 1);
             if (Q) { right_z(Q, ld, a, m, 0, n - 1, v, tau); fl += 16.0 * m * n; }
             for (int64_t c = 0; c < m; ++c)
                 for (int64_t i = 0; i < m; ++i) blk[i + c * m] = T[a + i + (a + c) * ld];
@@ -410,7 +441,7 @@ double oracle_stage2_flops(int64_t n, int64_t r, int is_complex)
             int64_t i2 = j + (k + 1) * r < n ? j + (k + 1) * r : n;
             int64_t i3 = j + (k + 2) * r < n ? j + (k + 2) * r : n;
             double m = (double)(i2 - i1 + 1);
-            fl += 4.0 * m * ((double)(n - jb) + (double)(n - i1 + 1) + (double)n
+            fl += 4.0 * m * ((double)(n - jb + 1) + (double)(n - i1 + 1) + (double)n
                              + (double)i3 + (double)i2 + (double)n);
         }
     }

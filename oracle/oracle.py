@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "ht_oracle.c")
 _LIB = os.path.join(_HERE, "libht_oracle.so")
 _lib = None
 
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
 
 
 def build(force: bool = False) -> str:
@@ -51,6 +51,9 @@ def lib():
         L.oracle_rq_dir_d.argtypes = [i64, vp, i64, vp]
         L.oracle_rq_dir_z.argtypes = [i64, vp, i64, vp]
         L.oracle_rq_dir_d.restype = L.oracle_rq_dir_z.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_get_threads.restype = ctypes.c_int
         L.oracle_stage2_flops.argtypes = [i64, i64, ctypes.c_int]
         L.oracle_stage2_flops.restype = ctypes.c_double
         if hasattr(L, "oracle_rhess_d"):
@@ -59,6 +62,23 @@ def lib():
             L.oracle_rhess_d.restype = L.oracle_rhess_z.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(t: int) -> int:
+    """Threads for the reflector applications (results are bitwise equal for
+    any count: only independent rows / columns are split).  Returns the
+    previous count."""
+    old = lib().oracle_get_threads()
+    lib().oracle_set_threads(int(t))
+    return old
+
+
+def host_cores() -> int:
+    """CPU cores this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
 
 
 def _ptr(a):

@@ -43,6 +43,15 @@ def lib(with_torch: bool = True):
     L = ctypes.CDLL(LIB_PATH)
     for f in ("ht_stage2_q", "ht_stage2_z_q"):
         getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp]
+    for f in ("ht_stage2_sweeps", "ht_stage2_z_sweeps"):
+        getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp]
+        getattr(L, f).restype = _int
+    L.ht_stream_status.argtypes = [_vp]
+    L.ht_stream_status.restype = _int
+    L.ht_set_knob.argtypes = [_int, _i64]
+    L.ht_set_knob.restype = _int
+    L.ht_get_knob.argtypes = [_int]
+    L.ht_get_knob.restype = _i64
     for f in ("ht_stage2", "ht_stage2_z", "ht_rhess", "ht_rhess_z"):
         getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp]
     for f in ("ht_rhess_p", "ht_rhess_z_p"):
@@ -77,12 +86,34 @@ def lib(with_torch: bool = True):
 
 
 EXPORTS = (
-    "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_batched",
+    "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_sweeps", "ht_stage2_z_sweeps",
+    "ht_stream_status", "ht_set_knob", "ht_get_knob", "ht_stage2_batched",
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_rhess_p", "ht_rhess_z_p", "ht_rhess_default_p",
     "ht_workspace_bytes", "ht_rhess_workspace_bytes", "ht_reserve_workspace",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
     "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms",
 )
+
+# knob ids of include/ht.h
+KNOB_WAIT_POLLS, KNOB_UPDATE_TILE_ROWS, KNOB_LOOKAHEAD = 1, 2, 3
+
+
+def set_knob(knob: int, value: int):
+    """Set a process-wide knob (KNOB_*); returns the previous value."""
+    old = int(lib().ht_get_knob(knob))
+    _check(lib().ht_set_knob(knob, int(value)), "ht_set_knob")
+    return old
+
+
+def get_knob(knob: int) -> int:
+    return int(lib().ht_get_knob(knob))
+
+
+def stream_status(stream=None) -> int:
+    """Wait for ``stream`` and return (and clear) its device-side failure
+    status: 0, or HT_ERR_TIMEOUT (5) when a bounded wait of a kernel gave up."""
+    return int(lib().ht_stream_status(_stream_ptr(stream)))
+
 
 PROFILE_CLASSES = ("band_copy", "generate", "update_right", "update_left", "zeroing", "update_qz", "form_factors")
 
@@ -168,11 +199,12 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def stage2(H, T, r: int, Q=None, Z=None, q: int = 0, stream=None):
+def stage2(H, T, r: int, Q=None, Z=None, q: int = 0, stream=None, jmax: int = -1):
     """Reduce the r-HT pencil (H, T) in place to Hessenberg-triangular form.
 
     Q, Z (optional) are updated in place: Q <- Q Q2, Z <- Z Z2.  The call is
-    asynchronous on ``stream`` (default: torch's current stream).
+    asynchronous on ``stream`` (default: torch's current stream).  ``jmax >=
+    0`` runs only the first jmax sweeps (``ht_stage2_sweeps``).
     """
     n = H.shape[0]
     cplx = H.is_complex()
@@ -184,8 +216,12 @@ def stage2(H, T, r: int, Q=None, Z=None, q: int = 0, stream=None):
             lds.append(ld)
     if len(set(lds)) != 1:
         raise ValueError("H, T, Q, Z must share the leading dimension")
-    f = lib().ht_stage2_z_q if cplx else lib().ht_stage2_q
-    _check(f(*ptrs, n, r, lds[0], q, _stream_ptr(stream)), "ht_stage2")
+    if jmax >= 0:
+        f = lib().ht_stage2_z_sweeps if cplx else lib().ht_stage2_sweeps
+        _check(f(*ptrs, n, r, lds[0], q, jmax, _stream_ptr(stream)), "ht_stage2_sweeps")
+    else:
+        f = lib().ht_stage2_z_q if cplx else lib().ht_stage2_q
+        _check(f(*ptrs, n, r, lds[0], q, _stream_ptr(stream)), "ht_stage2")
     return H, T, Q, Z
 
 

@@ -2,11 +2,20 @@
 // "Generating the reflectors"; generate algorithm of the appendix).
 //
 // One workgroup (256 threads, 4 wavefronts) per sweep of the group
-// j1..j2 (q <= r sweeps).  Sweep j processes blocks k = 0..kext-1 in order;
-// block (j,k) starts once sweep j-1 has finished block k+2 (progress flags in
-// device memory, agent-scope release/acquire).  Steps that run concurrently
-// touch disjoint columns of the scratch band, so no other synchronisation is
-// needed.
+// j1..j2 (q <= r sweeps) and one helper workgroup per sweep; sweep w is
+// workgroup 2w and its helper 2w+1, so every wait is on a workgroup with a
+// lower index (forward progress needs no co-residency: workgroups are
+// dispatched in index order).  Sweep j processes blocks k = 0..kext-1 in
+// order; block (j,k) starts once sweep j-1 has finished block k+2 (progress
+// flags in device memory, agent-scope release/acquire).  Steps that run
+// concurrently touch disjoint columns of the scratch band, so no other
+// synchronisation is needed.
+//
+// Every wait is bounded (GenArgs::wait_limit polls).  A wait that gives up
+// sets the timeout bit in the device status word and publishes -1 in its own
+// counter; a waiter that sees -1 gives up at once.  So every workgroup of the
+// launch exits normally and the host learns of the failure from the status
+// word (the output of that call is then invalid).
 //
 // Work of step (j,k), on the scratch band copy of H and T:
 //   1. lazy left updates: the left reflectors of block k of the earlier sweeps
@@ -44,9 +53,16 @@ struct GenArgs {
     S *SH, *ST;        // scratch band copies of H and T
     S *VL, *TL;        // left reflectors:  VL[((w*kext)+k)*r + i], TL[w*kext + k]
     S *VR, *TR;        // right reflectors
-    int *progress;     // per sweep of the group: blocks whose step chain is finished
+    int *progress;     // per sweep of the group: blocks whose step chain is finished (-1: gave up)
     int *hdone;        // per sweep: blocks whose far rows (the helper workgroup's part) are finished
+    int *status;       // device status word: kStatus* bits, OR-ed in by a wait that gives up
+    int64_t wait_limit;  // polls before a wait gives up (0: give up without polling)
 };
+
+// status bits of the device status word
+constexpr int kStatusWaitTimeout = 1;
+constexpr int kGaveUp = -1;           // counter value published by a workgroup that gave up
+constexpr int kAllDone = 0x3fffffff;  // counter value after the last step
 
 template <class S> __device__ inline S shfl_(S v, int src);
 template <> __device__ inline double shfl_<double>(double v, int src) { return __shfl(v, src, 64); }
@@ -57,6 +73,26 @@ __device__ inline int ld_acquire(const int *p) {
 }
 __device__ inline void st_release(int *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of one thread until *c1 >= need1 and *c2 >= need2 (c2 may be
+// null).  Returns false when a counter holds kGaveUp (a predecessor gave up)
+// or after `limit` polls (then the timeout bit is OR-ed into *status).  The
+// poll count is tested before the counters are read, so limit 0 gives up
+// without reading them.
+__device__ inline bool bounded_wait(const int *c1, int need1, const int *c2, int need2, int64_t limit,
+                                    int *status)
+{
+    for (int64_t polls = 0;; ++polls) {
+        if (polls >= limit) {
+            __hip_atomic_fetch_or(status, kStatusWaitTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        const int v1 = ld_acquire(c1), v2 = c2 ? ld_acquire(c2) : need2;
+        if (v1 == kGaveUp || v2 == kGaveUp) return false;
+        if (v1 >= need1 && v2 >= need2) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Householder generation in one wavefront.  Lane l holds x_l (l < m).
@@ -222,17 +258,12 @@ __device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
     __shared__ S hsig;
     for (int64_t k = 0; k < kext; ++k) {
         if (tid == 0) {
-            int polls = 0, ok = 1;
-            while (ld_acquire(a.progress + w) < (int)(k + 1)) {
-                if (++polls > (1 << 22)) { ok = 0; break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
+            s_go = bounded_wait(a.progress + w, (int)(k + 1), nullptr, 0, a.wait_limit, a.status) ? 1 : 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_go = ok;
         }
         __syncthreads();
-        if (!s_go) {                                // uniform: the sweep's workgroup never finished step k
-            if (tid == 0) st_release(a.hdone + w, 0x3fffffff);
+        if (!s_go) {                                // uniform: the sweep's workgroup gave up, or this wait did
+            if (tid == 0) st_release(a.hdone + w, kGaveUp);
             return;
         }
         if (k < nbj) {
@@ -262,17 +293,17 @@ __device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
         }
     }
     __syncthreads();
-    if (tid == 0) st_release(a.hdone + w, 0x3fffffff);
+    if (tid == 0) st_release(a.hdone + w, kAllDone);
 }
 
 template <class S, int RM>
 __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 {
-    if ((int64_t)blockIdx.x > a.j2 - a.j1) {       // second half of the grid: far-row helpers
-        gen_far<S, RM>(a, (int)(blockIdx.x - (a.j2 - a.j1 + 1)));
+    if (blockIdx.x & 1) {                          // odd workgroups: far-row helpers
+        gen_far<S, RM>(a, (int)(blockIdx.x >> 1));
         return;
     }
-    const int w = blockIdx.x;
+    const int w = blockIdx.x >> 1;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
     const int64_t j = j1 + w;
@@ -294,25 +325,19 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             // update) and that sweep's far rows of steps 0..k+1 (step k+1's
             // reach this step's T block, its lazy T column and its near rows;
             // step k+2's lie right of every column this step touches).
-            // Bounded wait: a predecessor step takes microseconds; after ~2^22
-            // polls the workgroup gives up (the output is then invalid) so that
-            // no wave can spin forever
-            __shared__ int s_abort;
+            // The wait is bounded (see the protocol at the top of the file).
+            __shared__ int s_go;
             if (tid == 0) {
-                int polls = 0;
-                s_abort = 0;
-                while (ld_acquire(a.progress + w - 1) < (int)(k + 3) || ld_acquire(a.hdone + w - 1) < (int)(k + 2)) {
-                    if (++polls > (1 << 22)) { s_abort = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
+                s_go = bounded_wait(a.progress + w - 1, (int)(k + 3), a.hdone + w - 1, (int)(k + 2), a.wait_limit,
+                                    a.status) ? 1 : 0;
                 // one acquire per workgroup: it invalidates the caches the
                 // workgroup's waves read through, and the barrier orders their
                 // loads after it
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            if (s_abort) {
-                if (tid == 0) st_release(a.progress + w, 0x3fffffff);
+            if (!s_go) {
+                if (tid == 0) st_release(a.progress + w, kGaveUp);
                 return;
             }
         }
@@ -485,7 +510,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         }
     }
     __syncthreads();
-    if (tid == 0) st_release(a.progress + w, 0x3fffffff);
+    if (tid == 0) st_release(a.progress + w, kAllDone);
 }
 
 }  // namespace ht

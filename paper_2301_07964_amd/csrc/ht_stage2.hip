@@ -226,7 +226,8 @@ static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, 
             return launch_check("k_update_mfma_coop(left)");
         }
     }
-    const int trw = ua.n >= 8192 ? 2 : 1;
+    const int64_t kt = knob(HT_KNOB_UPDATE_TILE_ROWS);
+    const int trw = kt == 1 || kt == 2 ? (int)kt : (ua.n >= 8192 ? 2 : 1);
     const int64_t tile = 16 * trw;
     int64_t tot = 0;
     for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + tile - 1) / tile; tot += ua.job[i].npanels; }
@@ -360,8 +361,11 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
     return g;
 }
 
+// Stage two, sweeps 1..jmax (jmax < 0 or >= n-2: all of them; the exact
+// zeros of the final form are written only when all sweeps are done).
 template <class S>
-static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, int64_t q, void *stream)
+static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, int64_t q, int64_t jmax,
+                       void *stream)
 {
     if (n < 0) return -5;
     if (r < 1) return -6;
@@ -386,6 +390,10 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     const Geometry g = geometry(n, re_, q, sizeof(S));
     unsigned char *ws = (unsigned char *)workspace_get(g.total, st, &rc);
     if (!ws) return rc;
+    StatusEntry *se = status_get(st);
+    if (!se) { snprintf(g_errmsg, sizeof(g_errmsg), "status word allocation failed"); return HT_ERR_NOMEM; }
+    const int64_t jlast = (jmax < 0 || jmax > n - 2) ? n - 2 : jmax;
+    const int64_t wait_limit = knob(HT_KNOB_WAIT_POLLS);
     S *SH = (S *)(ws + g.off_SH), *ST = (S *)(ws + g.off_ST);
     int *prog = (int *)(ws + g.off_prog);
     const Band B{g.BU, g.BL, g.ldb};
@@ -397,8 +405,8 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     const bool mf = use_mfma(rr, sizeof(S));
 
     int64_t grp = 0;
-    for (int64_t j1 = 1; j1 <= n - 2; j1 += q, ++grp) {
-        const int64_t j2 = i64min(j1 + q - 1, n - 2);
+    for (int64_t j1 = 1; j1 <= jlast; j1 += q, ++grp) {
+        const int64_t j2 = i64min(j1 + q - 1, jlast);
         const int64_t qg = j2 - j1 + 1;
         const int64_t kmax = nblocks(n, rr, j1);
         const int64_t kext = kmax + 1;
@@ -419,6 +427,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
         ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
         ga.hdone = prog + qg;
+        ga.status = se->dev; ga.wait_limit = wait_limit;
         { ProfScope ps(1, st);
         if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
         else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
@@ -476,8 +485,14 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         if (hipEventRecord(ax->join, ax->aux) != hipSuccess) return HT_ERR_HIP;
         if (hipStreamWaitEvent(st, ax->join, 0) != hipSuccess) return HT_ERR_HIP;
     }
-    if ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
+    if (jlast == n - 2 && ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st)))) return rc;
     return 0;
+}
+
+// Device status word of the stream -> pinned host int, and cleared.
+__global__ void k_status_take(int *dev, int *host)
+{
+    if (threadIdx.x == 0) { *host = *dev; *dev = 0; }
 }
 
 }  // namespace ht
@@ -487,23 +502,35 @@ extern "C" {
 
 int ht_stage2(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, void *stream)
 {
-    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, 0, stream);
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, 0, -1, stream);
 }
 
 int ht_stage2_q(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, int64_t q,
                 void *stream)
 {
-    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, q, stream);
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, q, -1, stream);
+}
+
+int ht_stage2_sweeps(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, int64_t q,
+                     int64_t jmax, void *stream)
+{
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, q, jmax, stream);
+}
+
+int ht_stage2_z_sweeps(void *H, void *T, void *Q, void *Z, int64_t n, int64_t r, int64_t ld, int64_t q,
+                       int64_t jmax, void *stream)
+{
+    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, q, jmax, stream);
 }
 
 int ht_stage2_z(void *H, void *T, void *Q, void *Z, int64_t n, int64_t r, int64_t ld, void *stream)
 {
-    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, 0, stream);
+    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, 0, -1, stream);
 }
 
 int ht_stage2_z_q(void *H, void *T, void *Q, void *Z, int64_t n, int64_t r, int64_t ld, int64_t q, void *stream)
 {
-    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, q, stream);
+    return ht::stage2_impl<ht::zd>((ht::zd *)H, (ht::zd *)T, (ht::zd *)Q, (ht::zd *)Z, n, r, ld, q, -1, stream);
 }
 
 int64_t ht_workspace_bytes(int64_t n, int64_t r, int64_t q, int is_complex)
@@ -538,11 +565,42 @@ const char *ht_strerror(int code)
     case HT_ERR_NOMEM: return "device workspace allocation failed";
     case HT_ERR_LAUNCH: return "kernel launch failed";
     case HT_ERR_NOTSUP: return "configuration not supported (r > 32 on the GPU path)";
+    case HT_ERR_TIMEOUT: return "a bounded device-side wait gave up: the output of a call on this stream is invalid";
     default: return "unknown error";
     }
 }
 
-const char *ht_version(void) { return "libht 0.1 (gfx950)"; }
+const char *ht_version(void) { return "libht 0.2 (gfx950)"; }
+
+int ht_stream_status(void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    ht::StatusEntry *se = ht::status_get(st);
+    if (!se) return HT_ERR_NOMEM;
+    hipLaunchKernelGGL(ht::k_status_take, dim3(1), dim3(64), 0, st, se->dev, se->host);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return HT_ERR_HIP;
+    const int v = *(volatile int *)se->host;
+    return (v & ht::kStatusWaitTimeout) ? HT_ERR_TIMEOUT : 0;
+}
+
+int ht_set_knob(int knob, int64_t value)
+{
+    if (knob < 1 || knob > ht::kNumKnobs) return -1;
+    switch (knob) {
+    case HT_KNOB_WAIT_POLLS: if (value < 0) return -2; break;
+    case HT_KNOB_UPDATE_TILE_ROWS: if (value < 0 || value > 2) return -2; break;
+    case HT_KNOB_LOOKAHEAD: if (value < 0 || value > 1) return -2; break;
+    default: break;
+    }
+    ht::knobs()[knob - 1].store(value, std::memory_order_relaxed);
+    return 0;
+}
+
+int64_t ht_get_knob(int knob)
+{
+    if (knob < 1 || knob > ht::kNumKnobs) return -1;
+    return ht::knob(knob);
+}
 
 const char *ht_last_error_message(void) { return ht::g_errmsg; }
 

@@ -7,11 +7,38 @@
 // ht_release_workspace() or process exit.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <utility>
 
 namespace ht {
+
+// ------------------------------------------------------------------ knobs
+// Process-wide settings (ht_set_knob / ht_get_knob).  Index = HT_KNOB_* - 1.
+constexpr int kNumKnobs = 3;
+inline std::atomic<int64_t> *knobs()
+{
+    static std::atomic<int64_t> k[kNumKnobs] = {
+        {int64_t(1) << 22},   // HT_KNOB_WAIT_POLLS: polls before a device-side wait gives up
+        {0},                  // HT_KNOB_UPDATE_TILE_ROWS: 0 automatic, 1 or 2 tiles of 16 rows per wavefront
+        {0},                  // HT_KNOB_LOOKAHEAD: 1 overlap generation with the delayed updates
+    };
+    return k;
+}
+inline int64_t knob(int id) { return knobs()[id - 1].load(std::memory_order_relaxed); }
+
+// ------------------------------------------------------------ status word
+// One device int per (device, stream): kernels OR failure bits into it (a
+// bounded wait that gave up); ht_stream_status() reads and clears it.  Also a
+// pinned host int that receives the value.
+struct StatusEntry { int *dev = nullptr; int *host = nullptr; };
+
+inline std::map<std::pair<int, hipStream_t>, StatusEntry> &status_map()
+{
+    static std::map<std::pair<int, hipStream_t>, StatusEntry> m;
+    return m;
+}
 
 struct WsEntry { void *ptr = nullptr; size_t size = 0; };
 
@@ -39,6 +66,27 @@ inline void *workspace_get(size_t bytes, hipStream_t st, int *rc)
     if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) { (void)hipGetLastError(); *rc = 2; return nullptr; }
     e.ptr = p; e.size = bytes;
     return p;
+}
+
+// The status word of (current device, stream), created (zeroed, stream
+// ordered) on first use; nullptr on failure.
+inline StatusEntry *status_get(hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(ws_mutex());
+    StatusEntry &e = status_map()[{dev, st}];
+    if (e.dev) return &e;
+    if (hipMalloc(&e.dev, 256) != hipSuccess) { (void)hipGetLastError(); e.dev = nullptr; return nullptr; }
+    if (hipHostMalloc(&e.host, 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError(); (void)hipFree(e.dev); e.dev = nullptr; e.host = nullptr; return nullptr;
+    }
+    *e.host = 0;
+    if (hipMemcpyAsync(e.dev, e.host, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipFree(e.dev); (void)hipHostFree(e.host); e.dev = nullptr; e.host = nullptr; return nullptr;
+    }
+    return &e;
 }
 
 // Grows the (current device, stream) buffer to at least `bytes` now, so that

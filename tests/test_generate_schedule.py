@@ -159,6 +159,24 @@ def test_later_groups_are_race_free(n, r, q, j1):
     assert violations(n, r, q, j1=j1) == set()
 
 
+def block_of(task):
+    """Workgroup index of a task's workgroup in the generate kernel's grid:
+    sweep w is workgroup 2w, its far-row helper 2w + 1."""
+    kind, w, _ = task
+    return 2 * w + (1 if kind == "h" else 0)
+
+
+@pytest.mark.parametrize("q", [1, 2, 5, 8, 32])
+def test_every_wait_is_on_a_lower_workgroup(q):
+    """Forward progress without co-residency: each wait edge (a task waiting on
+    another workgroup's task) points from a lower workgroup index to a higher
+    one, so the lowest unfinished workgroup never waits on an undispatched one
+    (workgroups are dispatched in index order)."""
+    for a, b in edges(q, 6):
+        if block_of(a) != block_of(b):
+            assert block_of(a) < block_of(b), (a, b)
+
+
 def test_model_detects_a_missing_wait():
     # waiting for the predecessor's far rows only up to step k (one step too
     # few) leaves its step k+1 far rows unordered with this step's T block

@@ -207,12 +207,38 @@ def _sweeps_gpu(H, T, r, q, jmax):
     return out
 
 
-def _compare(got, ref, what):
+def _compare(got, ref, what, floor=(0.0, 0.0)):
+    """H, T, Q, Z against the oracle: relative Frobenius error within
+    max(1e-9, 10 x floor[0]) and entry-wise error (relative to the largest
+    entry) within max(1e-9, 10 x floor[1]), where `floor` is the oracle's own
+    response to a rounding-level perturbation of its input (see
+    sensitivity_floor)."""
     errs = [rel(g, o) for g, o in zip(got, ref[:4])]
     emax = [rel_max(g, o) for g, o in zip(got, ref[:4])]
-    print(f"[parity] {what}: rel H,T,Q,Z = {errs}; entry-wise = {emax}", flush=True)
-    assert max(errs) <= TOL, errs
-    assert max(emax) <= TOL, emax
+    bf, bm = max(TOL, 10 * floor[0]), max(TOL, 10 * floor[1])
+    print(f"[parity] {what}: rel H,T,Q,Z = {errs}; entry-wise = {emax}; floor {floor}; bounds {bf:.2e} {bm:.2e}",
+          flush=True)
+    assert max(errs) <= bf, errs
+    assert max(emax) <= bm, emax
+
+
+def sensitivity_floor(H, T, r, ref, jmax=-1):
+    """How far the oracle's own H, T, Q, Z move when the band of H is perturbed
+    by 1e-15 relative (a few units of rounding per entry): (max relative
+    Frobenius change, max entry-wise change relative to the largest entry).
+    Reordering the arithmetic, as the delayed updates do, perturbs at that
+    level, so no implementation can be asked to agree more closely."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(1)
+    P = rng.standard_normal(H.shape)
+    if np.iscomplexobj(H):
+        P = P + 1j * rng.standard_normal(H.shape)
+    Hp = H + 1e-15 * np.abs(H) * P
+    del P
+    ref2 = O.stage2(Hp, T, r, jmax=jmax)
+    del Hp
+    return (max(rel(a, b) for a, b in zip(ref2[:4], ref[:4])),
+            max(rel_max(a, b) for a, b in zip(ref2[:4], ref[:4])))
 
 
 @pytest.mark.parametrize("n", [8192, 16384])
@@ -220,7 +246,14 @@ def test_parity_first_two_groups_at_full_size(n):
     """The headline shapes (r = q = 32, real): the first two groups of sweeps
     (jmax = 64) of the GPU path at n = 8192 and n = 16384 against the oracle's
     first 64 sweeps.  At these sizes the matrix-core right update runs with two
-    16-row tiles per wavefront, the variant the full reductions use."""
+    16-row tiles per wavefront, the variant the full reductions use.
+
+    These pencils are sensitive: a 1e-15 relative perturbation of H's band
+    moves the oracle's own result by about 5e-10 (Frobenius) and 8e-9
+    (largest entry) at n = 8192, and 5e-9 and 1.3e-7 at n = 16384, where
+    near-singular diagonal blocks of T make the direction of the opposite
+    reflector ill-determined.  The bound is therefore 10x that floor,
+    measured here on the same input, and 1e-9 where the floor is lower."""
     from oracle import oracle as O
     r = q = 32
     jmax = 64
@@ -230,10 +263,11 @@ def test_parity_first_two_groups_at_full_size(n):
     old = O.set_threads(oracle_threads())
     try:
         ref = O.stage2(H, T, r, jmax=jmax)
+        floor = sensitivity_floor(H, T, r, ref, jmax)
     finally:
         O.set_threads(old)
     del H, T
-    _compare(got, ref, f"n={n} r={r} jmax={jmax}")
+    _compare(got, ref, f"n={n} r={r} jmax={jmax}", floor)
     # the structure after 64 sweeps: columns 1..64 of H reduced
     assert np.all(np.tril(got[0][:, :jmax], -2) == 0)
 
@@ -253,7 +287,8 @@ def test_parity_two_row_tiles(n, r, seed):
 
 def test_parity_full_reduction_n4096_r16():
     """The n = 4096, r = 16 workload reduced completely (Q, Z accumulated),
-    against the oracle run on the host cores (bitwise equal to one thread)."""
+    against the oracle run on the host cores (bitwise equal to one thread),
+    within 10x the oracle's own sensitivity floor (1e-9 where that is lower)."""
     from oracle import oracle as O
     n, r = 4096, 16
     H, T = inputs.rht_pencil(n, r, 0)
@@ -261,9 +296,10 @@ def test_parity_full_reduction_n4096_r16():
     old = O.set_threads(oracle_threads())
     try:
         ref = O.stage2(H, T, r)
+        floor = sensitivity_floor(H, T, r, ref)
     finally:
         O.set_threads(old)
-    _compare(got, ref, f"n={n} r={r} full")
+    _compare(got, ref, f"n={n} r={r} full", floor)
     assert np.all(np.tril(got[0], -2) == 0) and np.all(np.tril(got[1], -1) == 0)
 
 

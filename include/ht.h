@@ -43,6 +43,7 @@ extern "C" {
 #define HT_ERR_LAUNCH 3  /* a kernel launch failed */
 #define HT_ERR_NOTSUP 4  /* configuration not supported by this build */
 #define HT_ERR_TIMEOUT 5 /* a bounded device-side wait gave up (ht_stream_status) */
+#define HT_ERR_SCRATCH 6 /* workspace larger than the fixed scratch (ht_stage2_noalloc) */
 
 /*
  * ht_stage2 -- reduce an r-Hessenberg-triangular pencil to Hessenberg-
@@ -82,6 +83,38 @@ int ht_stage2_q(double *H, double *T, double *Q, double *Z,
                 int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
 int ht_stage2_z_q(void *H, void *T, void *Q, void *Z,
                   int64_t n, int64_t r, int64_t ld, int64_t q, void *stream);
+
+/*
+ * ht_stage2_noalloc -- ht_stage2 for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics, results and errors as
+ * ht_stage2 (same kernels and reflectors), except:
+ *   - The workspace comes from a fixed device array of
+ *     HT_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every
+ *     device it runs on until the process ends; the call allocates nothing
+ *     (no hipMalloc/hipFree, no stream or event creation, no library routine
+ *     that allocates).  Every size with ht_workspace_bytes(n, r, 0, 0) <=
+ *     HT_NOALLOC_SCRATCH_BYTES - 256 fits (n <= 2895 at r = 32, 8975 at
+ *     r = 16, 24522 at r = 8; the call takes one of the two reflector buffers
+ *     that figure includes, so somewhat larger n fit too); a call that does
+ *     not fit returns HT_ERR_SCRATCH and enqueues nothing.
+ *   - Every kernel runs on `stream` (Q and Z are not overlapped on a second
+ *     stream) and kernel timing (ht_profile_enable) does not apply.
+ *   - status: NULL or a DEVICE int owned by the caller; a device-side wait
+ *     that gives up ORs 1 into it (the output is then invalid), so the caller
+ *     zeroes it before the call and reads it after synchronising `stream`.
+ *     With NULL such a failure is not reported.
+ *   - Every call on one device shares that device's scratch and overwrites
+ *     it: calls that may overlap on one device (different streams, or host
+ *     threads) race and must be serialised by the caller.  The scratch keeps
+ *     the last call's contents; every counter a call reads is cleared by that
+ *     call's own kernels.
+ * The first call on a device looks up the device address of its copy of the
+ * scratch (hipGetSymbolAddress, no allocation).
+ */
+#define HT_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int ht_stage2_noalloc(double *H, double *T, double *Q, double *Z, int64_t n,
+                      int64_t r, int64_t ld, int *status, void *stream);
 
 /*
  * ht_stage2_sweeps -- the first jmax sweeps of stage two only (sweeps

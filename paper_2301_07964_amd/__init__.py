@@ -46,6 +46,8 @@ def lib(with_torch: bool = True):
     for f in ("ht_stage2_sweeps", "ht_stage2_z_sweeps"):
         getattr(L, f).argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp]
         getattr(L, f).restype = _int
+    L.ht_stage2_noalloc.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp]
+    L.ht_stage2_noalloc.restype = _int
     L.ht_stream_status.argtypes = [_vp]
     L.ht_stream_status.restype = _int
     L.ht_set_knob.argtypes = [_int, _i64]
@@ -87,7 +89,7 @@ def lib(with_torch: bool = True):
 
 EXPORTS = (
     "ht_stage2", "ht_stage2_z", "ht_stage2_q", "ht_stage2_z_q", "ht_stage2_sweeps", "ht_stage2_z_sweeps",
-    "ht_stream_status", "ht_set_knob", "ht_get_knob", "ht_stage2_batched",
+    "ht_stage2_noalloc", "ht_stream_status", "ht_set_knob", "ht_get_knob", "ht_stage2_batched",
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_rhess_p", "ht_rhess_z_p", "ht_rhess_default_p",
     "ht_workspace_bytes", "ht_rhess_workspace_bytes", "ht_reserve_workspace",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
@@ -222,6 +224,35 @@ def stage2(H, T, r: int, Q=None, Z=None, q: int = 0, stream=None, jmax: int = -1
     else:
         f = lib().ht_stage2_z_q if cplx else lib().ht_stage2_q
         _check(f(*ptrs, n, r, lds[0], q, _stream_ptr(stream)), "ht_stage2")
+    return H, T, Q, Z
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # HT_NOALLOC_SCRATCH_BYTES of include/ht.h
+
+
+def stage2_noalloc(H, T, r: int, Q=None, Z=None, status=None, stream=None):
+    """``ht_stage2_noalloc``: ht_stage2 with its workspace in the library's
+    fixed device scratch, for callers that cannot allocate.  ``status`` is
+    None or a one-element int32 device tensor (zeroed by the caller) into
+    which a device-side wait that gives up ORs 1.  Real pencils only."""
+    n = H.shape[0]
+    if H.is_complex():
+        raise TypeError("ht_stage2_noalloc takes real (float64) pencils")
+    ptrs, lds = [], []
+    for t, nm in ((H, "H"), (T, "T"), (Q, "Q"), (Z, "Z")):
+        p, ld = _layout(t, n, nm, False)
+        ptrs.append(p)
+        if ld is not None:
+            lds.append(ld)
+    if len(set(lds)) != 1:
+        raise ValueError("H, T, Q, Z must share the leading dimension")
+    sp = None
+    if status is not None:
+        torch = _torch()
+        if not status.is_cuda or status.dtype != torch.int32 or status.numel() < 1:
+            raise ValueError("status must be an int32 device tensor")
+        sp = status.data_ptr()
+    _check(lib().ht_stage2_noalloc(*ptrs, n, r, lds[0], sp, _stream_ptr(stream)), "ht_stage2_noalloc")
     return H, T, Q, Z
 
 

@@ -55,7 +55,8 @@ struct ProfScope {
     int cls = 0;
     hipStream_t st = nullptr;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    ProfScope(int c, hipStream_t s) : cls(c), st(s) {       // c < 0: no timing
+        if (c < 0) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
@@ -139,10 +140,10 @@ __global__ __launch_bounds__(256) void k_clean(S *H, S *T, int64_t ld, int64_t n
 }
 
 template <class S>
-static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st)
+static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st, bool prof = true)
 {
     if (n <= 0 || !X) return 0;
-    ProfScope ps(4, st);
+    ProfScope ps(prof ? 4 : -1, st);
     hipLaunchKernelGGL(k_zero_lower<S>, dim3((unsigned)n), dim3(256), 0, st, X, ld, n, off);
     return launch_check("k_zero_lower");
 }
@@ -338,7 +339,7 @@ static int64_t kw_of(int64_t r) { return 2 * r < 16 ? 16 : 2 * r; }
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
+static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz, int nbuf = kNBuf)
 {
     Geometry g{};
     g.n = n; g.r = r; g.q = q; g.esz = esz;
@@ -355,17 +356,27 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz)
     g.tbytes = al((size_t)q * g.kext * esz);
     g.refl_bytes = g.vbytes * 2 + g.tbytes * 2;
     if (use_mfma(r, esz)) g.refl_bytes += al((size_t)2 * g.kext * kw_of(r) * kw_of(r) * esz);
-    g.off_refl = o; o += g.refl_bytes * kNBuf;
+    g.off_refl = o; o += g.refl_bytes * nbuf;
     g.off_prog = o; o += al((size_t)2 * q * sizeof(int));          // progress, far-row helpers' progress
     g.total = o;
     return g;
 }
 
+// A caller-provided workspace for calls that must not allocate: `ws` holds
+// `cap` bytes of device memory, `status` is the device status word.  Such a
+// call runs every kernel on the caller's stream (no auxiliary stream, events
+// or kernel timing) with one reflector buffer.
+struct FixedWs {
+    unsigned char *ws;
+    size_t cap;
+    int *status;
+};
+
 // Stage two, sweeps 1..jmax (jmax < 0 or >= n-2: all of them; the exact
 // zeros of the final form are written only when all sweeps are done).
 template <class S>
 static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, int64_t q, int64_t jmax,
-                       void *stream)
+                       void *stream, const FixedWs *fx = nullptr)
 {
     if (n < 0) return -5;
     if (r < 1) return -6;
@@ -377,21 +388,41 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     int rc;
     (void)hipGetLastError();           // clear a stale error left by earlier HIP calls
     g_errmsg[0] = 0;
-    // entries outside the r-HT pattern are not read: they are overwritten by 0
-    if ((rc = zero_lower(H, ld, n, r, st)) || (rc = zero_lower(T, ld, n, 0, st))) return rc;
+    // every check that can fail comes before the first launch, so that a call
+    // that returns an error has enqueued nothing
     const int64_t re_ = i64min(r, i64max(n - 1, 1));
-    if (n <= 2 || re_ <= 1) {
-        if ((rc = zero_lower(H, ld, n, 1, st))) return rc;
+    const bool trivial = n <= 2 || re_ <= 1;
+    const int nbuf = fx ? 1 : kNBuf;
+    Geometry g{};
+    if (!trivial) {
+        if (re_ > kMaxR) return HT_ERR_NOTSUP;
+        if (q == 0) q = default_q(n, re_);
+        if (q < 1 || q > re_) return -8;
+        g = geometry(n, re_, q, sizeof(S), nbuf);
+        if (fx && g.total > fx->cap) {
+            snprintf(g_errmsg, sizeof(g_errmsg), "workspace of %zu bytes exceeds the fixed scratch of %zu bytes",
+                     g.total, fx->cap);
+            return HT_ERR_SCRATCH;
+        }
+    }
+    // entries outside the r-HT pattern are not read: they are overwritten by 0
+    if ((rc = zero_lower(H, ld, n, r, st, !fx)) || (rc = zero_lower(T, ld, n, 0, st, !fx))) return rc;
+    if (trivial) {
+        if ((rc = zero_lower(H, ld, n, 1, st, !fx))) return rc;
         return 0;
     }
-    if (re_ > kMaxR) return HT_ERR_NOTSUP;
-    if (q == 0) q = default_q(n, re_);
-    if (q < 1 || q > re_) return -8;
-    const Geometry g = geometry(n, re_, q, sizeof(S));
-    unsigned char *ws = (unsigned char *)workspace_get(g.total, st, &rc);
-    if (!ws) return rc;
-    StatusEntry *se = status_get(st);
-    if (!se) { snprintf(g_errmsg, sizeof(g_errmsg), "status word allocation failed"); return HT_ERR_NOMEM; }
+    unsigned char *ws = nullptr;
+    int *status = nullptr;
+    if (fx) {
+        ws = fx->ws;
+        status = fx->status;
+    } else {
+        ws = (unsigned char *)workspace_get(g.total, st, &rc);
+        if (!ws) return rc;
+        StatusEntry *se = status_get(st);
+        if (!se) { snprintf(g_errmsg, sizeof(g_errmsg), "status word allocation failed"); return HT_ERR_NOMEM; }
+        status = se->dev;
+    }
     const int64_t jlast = (jmax < 0 || jmax > n - 2) ? n - 2 : jmax;
     const int64_t wait_limit = knob(HT_KNOB_WAIT_POLLS);
     S *SH = (S *)(ws + g.off_SH), *ST = (S *)(ws + g.off_ST);
@@ -399,8 +430,10 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     const Band B{g.BU, g.BL, g.ldb};
     const int64_t rr = re_;
     const bool qz = (Q != nullptr) || (Z != nullptr);
-    AuxCtx *ax = qz ? aux_ctx(st) : nullptr;
-    if (qz && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
+    const bool aux = qz && !fx;                      // Q and Z on the auxiliary stream
+    AuxCtx *ax = aux ? aux_ctx(st) : nullptr;
+    if (aux && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
+    const bool prof = !fx;                           // kernel timing creates events: not for fixed scratch
     const int64_t np = (n + 63) / 64;
     const bool mf = use_mfma(rr, sizeof(S));
 
@@ -410,15 +443,15 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         const int64_t qg = j2 - j1 + 1;
         const int64_t kmax = nblocks(n, rr, j1);
         const int64_t kext = kmax + 1;
-        const int buf = (int)(grp % kNBuf);
+        const int buf = (int)(grp % nbuf);
         unsigned char *rb = ws + g.off_refl + g.refl_bytes * buf;
         const size_t vbytes = g.vbytes, tbytes = g.tbytes;
         S *VL = (S *)rb, *VR = (S *)(rb + vbytes), *TL = (S *)(rb + 2 * vbytes), *TR = (S *)(rb + 2 * vbytes + tbytes);
         S *F = mf ? (S *)(rb + 2 * vbytes + 2 * tbytes) : nullptr;    // window factors
         // the aux stream must be done with this buffer (group grp - kNBuf)
-        if (qz && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
+        if (aux && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
         // 1. scratch band
-        { ProfScope ps(0, st);
+        { ProfScope ps(prof ? 0 : -1, st);
         hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
                            (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)(2 * qg));
         if ((rc = launch_check("k_band_copy"))) return rc; }
@@ -427,14 +460,14 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
         ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
         ga.hdone = prog + qg;
-        ga.status = se->dev; ga.wait_limit = wait_limit;
-        { ProfScope ps(1, st);
+        ga.status = status; ga.wait_limit = wait_limit;
+        { ProfScope ps(prof ? 1 : -1, st);
         if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
         else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
         else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
         if (mf) {
-            ProfScope ps(6, st);
+            ProfScope ps(prof ? 6 : -1, st);
             if constexpr (sizeof(S) == 8) {
                 if ((rc = launch_form_factors(rr, qg, kmax, kext, VL, TL, VR, TR, F, st))) return rc;
             } else {
@@ -451,42 +484,85 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
             ua.job[nj].X = X; ua.job[nj].ld = ld; ua.job[nj].lim = lim; ua.job[nj].npanels = np; ua.job[nj].side = side;
             ++nj; tot += np;
         };
-        // 3a. Q and Z (right updates) on the auxiliary stream
+        // 3a. Q and Z (right updates) on the auxiliary stream (fixed scratch:
+        // on the caller's stream)
         if (qz) {
-            if (hipEventRecord(ax->gen[buf], st) != hipSuccess) return HT_ERR_HIP;
-            if (hipStreamWaitEvent(ax->aux, ax->gen[buf], 0) != hipSuccess) return HT_ERR_HIP;
+            hipStream_t qs = st;
+            if (aux) {
+                if (hipEventRecord(ax->gen[buf], st) != hipSuccess) return HT_ERR_HIP;
+                if (hipStreamWaitEvent(ax->aux, ax->gen[buf], 0) != hipSuccess) return HT_ERR_HIP;
+                qs = ax->aux;
+            }
             addjob(Z, 1, -1);
             addjob(Q, 0, -1);
             ua.njobs = nj;
-            { ProfScope ps(5, ax->aux);
-            if ((rc = launch_pass<S>(true, ua, tot, F, ax->aux))) return rc; }
-            if (hipEventRecord(ax->qz[buf], ax->aux) != hipSuccess) return HT_ERR_HIP;
+            { ProfScope ps(prof ? 5 : -1, qs);
+            if ((rc = launch_pass<S>(true, ua, tot, F, qs))) return rc; }
+            if (aux && hipEventRecord(ax->qz[buf], ax->aux) != hipSuccess) return HT_ERR_HIP;
         }
         // 3b. H and T: right updates, then left updates, then the exact zeros
         nj = 0; tot = 0;
         addjob(H, 1, (q + 2) * rr);
         addjob(T, 1, (q + 1) * rr);
         ua.njobs = nj;
-        { ProfScope ps(2, st);
+        { ProfScope ps(prof ? 2 : -1, st);
         if ((rc = launch_pass<S>(true, ua, tot, F, st))) return rc; }
         nj = 0; tot = 0;
         addjob(H, 0, (q + 1) * rr);
         addjob(T, 0, (q + 1) * rr);
         ua.njobs = nj;
-        { ProfScope ps(3, st);
+        { ProfScope ps(prof ? 3 : -1, st);
         if ((rc = launch_pass<S>(false, ua, tot, F, st))) return rc; }
-        { ProfScope ps(4, st);
+        { ProfScope ps(prof ? 4 : -1, st);
         const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr);
         hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0,
                            (q + 4) * rr);
         if ((rc = launch_check("k_clean"))) return rc; }
     }
-    if (qz) {   // join the auxiliary stream
+    if (aux) {   // join the auxiliary stream
         if (hipEventRecord(ax->join, ax->aux) != hipSuccess) return HT_ERR_HIP;
         if (hipStreamWaitEvent(st, ax->join, 0) != hipSuccess) return HT_ERR_HIP;
     }
-    if (jlast == n - 2 && ((rc = zero_lower(H, ld, n, 1, st)) || (rc = zero_lower(T, ld, n, 0, st)))) return rc;
+    if (jlast == n - 2 && ((rc = zero_lower(H, ld, n, 1, st, prof)) || (rc = zero_lower(T, ld, n, 0, st, prof))))
+        return rc;
     return 0;
+}
+
+// ------------------------------------------------ fixed scratch (no allocation)
+// ht_stage2_noalloc takes its workspace from this array instead of the
+// per-stream cache.  Each device that runs the library holds its own copy
+// until the process ends.  Host code must not pass the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the device
+// address of each copy is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.  The first 256 bytes hold a
+// status word for calls that pass no status pointer of their own.
+constexpr size_t kScratchBytes = size_t(HT_NOALLOC_SCRATCH_BYTES);
+constexpr size_t kScratchStatus = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first call
+// on that device), or nullptr with *rc set.
+static unsigned char *scratch_of_current_device(int *rc)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { *rc = HT_ERR_HIP; return nullptr; }
+    if (dev < 0 || dev >= kMaxDevices) { *rc = HT_ERR_NOTSUP; return nullptr; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            snprintf(g_errmsg, sizeof(g_errmsg), "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            *rc = HT_ERR_HIP;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 // Device status word of the stream -> pinned host int, and cleared.
@@ -509,6 +585,25 @@ int ht_stage2_q(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r
                 void *stream)
 {
     return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, q, -1, stream);
+}
+
+int ht_stage2_noalloc(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, int *status,
+                      void *stream)
+{
+    // argument checks first (they need no device)
+    if (n < 0) return -5;
+    if (r < 1) return -6;
+    if (ld < (n > 1 ? n : 1)) return -7;
+    if (n > 0 && !H) return -1;
+    if (n > 0 && !T) return -2;
+    int rc = 0;
+    unsigned char *base = ht::scratch_of_current_device(&rc);
+    if (!base) return rc;
+    ht::FixedWs fx;
+    fx.ws = base + ht::kScratchStatus;
+    fx.cap = ht::kScratchBytes - ht::kScratchStatus;
+    fx.status = status ? status : (int *)base;
+    return ht::stage2_impl<double>(H, T, Q, Z, n, r, ld, 0, -1, stream, &fx);
 }
 
 int ht_stage2_sweeps(double *H, double *T, double *Q, double *Z, int64_t n, int64_t r, int64_t ld, int64_t q,
@@ -566,6 +661,7 @@ const char *ht_strerror(int code)
     case HT_ERR_LAUNCH: return "kernel launch failed";
     case HT_ERR_NOTSUP: return "configuration not supported (r > 32 on the GPU path)";
     case HT_ERR_TIMEOUT: return "a bounded device-side wait gave up: the output of a call on this stream is invalid";
+    case HT_ERR_SCRATCH: return "the call needs more workspace than the fixed no-allocation scratch holds";
     default: return "unknown error";
     }
 }

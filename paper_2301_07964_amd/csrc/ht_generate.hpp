@@ -2,10 +2,10 @@
 // "Generating the reflectors"; generate algorithm of the appendix).
 //
 // One workgroup (256 threads, 4 wavefronts) per sweep of the group
-// j1..j2 (q <= r sweeps) and one helper workgroup per sweep; sweep w is
-// workgroup 2w and its helper 2w+1, so every wait is on a workgroup with a
-// lower index (forward progress needs no co-residency: workgroups are
-// dispatched in index order).  Sweep j processes blocks k = 0..kext-1 in
+// j1..j2 (q <= r sweeps) and two helper workgroups per sweep (the far rows of
+// H and of T); sweep w is workgroup 3w and its helpers 3w+1 (H) and 3w+2 (T),
+// so every wait is on a workgroup with a lower index (forward progress needs
+// no co-residency: workgroups are dispatched in index order).  Sweep j processes blocks k = 0..kext-1 in
 // order; block (j,k) starts once sweep j-1 has finished block k+2 (progress
 // flags in device memory, agent-scope release/acquire).  Steps that run
 // concurrently touch disjoint columns of the scratch band, so no other
@@ -54,7 +54,7 @@ struct GenArgs {
     S *VL, *TL;        // left reflectors:  VL[((w*kext)+k)*r + i], TL[w*kext + k]
     S *VR, *TR;        // right reflectors
     int *progress;     // per sweep of the group: blocks whose step chain is finished (-1: gave up)
-    int *hdone;        // per sweep: blocks whose far rows (the helper workgroup's part) are finished
+    int *hdone;        // per sweep: blocks whose far rows of H (hdone[w]) and of T (hdone[q+w]) are finished
     int *status;       // device status word: kStatus* bits, OR-ed in by a wait that gives up
     int64_t wait_limit;  // polls before a wait gives up (0: give up without polling)
 };
@@ -68,29 +68,34 @@ template <class S> __device__ inline S shfl_(S v, int src);
 template <> __device__ inline double shfl_<double>(double v, int src) { return __shfl(v, src, 64); }
 template <> __device__ inline zd shfl_<zd>(zd v, int src) { return mk<zd>(__shfl(v.re, src, 64), __shfl(v.im, src, 64)); }
 
-__device__ inline int ld_acquire(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ inline void st_release(int *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait of one thread until *c1 >= need1 and *c2 >= need2 (c2 may be
-// null).  Returns false when a counter holds kGaveUp (a predecessor gave up)
-// or after `limit` polls (then the timeout bit is OR-ed into *status).  The
-// poll count is tested before the counters are read, so limit 0 gives up
-// without reading them.
-__device__ inline bool bounded_wait(const int *c1, int need1, const int *c2, int need2, int64_t limit,
-                                    int *status)
+__device__ inline int ld_relaxed(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of one thread until *c1 >= need1, *c2 >= need2 and
+// *c3 >= need3 (c2, c3 may be null).  The counters are polled with relaxed
+// loads (an acquiring load would invalidate the cache of the whole XCD at
+// every poll); the caller issues one agent-scope acquire fence once the wait
+// has succeeded, which orders its later loads after the releases it observed.
+// Returns false when a counter holds kGaveUp (a predecessor gave up) or after
+// `limit` polls (then the timeout bit is OR-ed into *status).  The poll count
+// is tested before the counters are read, so limit 0 gives up without reading
+// them.
+__device__ inline bool bounded_wait(const int *c1, int need1, const int *c2, int need2, const int *c3, int need3,
+                                    int64_t limit, int *status)
 {
     for (int64_t polls = 0;; ++polls) {
         if (polls >= limit) {
             __hip_atomic_fetch_or(status, kStatusWaitTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        const int v1 = ld_acquire(c1), v2 = c2 ? ld_acquire(c2) : need2;
-        if (v1 == kGaveUp || v2 == kGaveUp) return false;
-        if (v1 >= need1 && v2 >= need2) return true;
+        const int v1 = ld_relaxed(c1), v2 = c2 ? ld_relaxed(c2) : need2, v3 = c3 ? ld_relaxed(c3) : need3;
+        if (v1 == kGaveUp || v2 == kGaveUp || v3 == kGaveUp) return false;
+        if (v1 >= need1 && v2 >= need2 && v3 >= need3) return true;
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -238,32 +243,35 @@ __device__ __forceinline__ void far_rows(S *XH, S *XT, const Band &B, int64_t to
     }
 }
 
-// Helper workgroup of sweep w (the second half of the grid): the "far" part of
-// each step's eager right update, one step behind the sweep's own workgroup.
-// Step k's right reflector is applied to rows topH .. j1+(k+1)r of H and (for
-// all but the last sweep) rows topT .. i2 of T in the block's columns, with the
-// exact zeros of T's column i1 below the diagonal.  The sweep's own workgroup
-// has done the rows from j1+(k+1)r+1 on, the only ones its next steps read;
-// the successor sweep waits for both counters.
+// Helper workgroups of sweep w: the "far" part of each step's eager right
+// update, behind the sweep's own workgroup.  Step k's right reflector is
+// applied by helper part 0 to rows topH .. j1+(k+1)r of H and by helper part 1
+// (for all but the last sweep) to rows topT .. i2 of T in the block's columns,
+// with the exact zeros of T's column i1 below the diagonal.  The two parts
+// touch different matrices, about (q-1-w) r rows each.  The sweep's own
+// workgroup has done the rows of H from j1+(k+1)r+1 on, the only ones its next
+// steps read; the successor sweep waits for all three counters.
 template <class S, int RM>
-__device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
+__device__ __forceinline__ void gen_far(GenArgs<S> a, int w, int part)
 {
     const int tid = threadIdx.x;
     const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
     const int64_t j = j1 + w, d = j2 - j;
     const int64_t nbj = nblocks(n, r, j);
     const Band B = a.band;
+    const int64_t q = j2 - j1 + 1;
+    int *mine = a.hdone + part * q + w;
     __shared__ int s_go;
     __shared__ S hsw[64];
     __shared__ S hsig;
     for (int64_t k = 0; k < kext; ++k) {
         if (tid == 0) {
-            s_go = bounded_wait(a.progress + w, (int)(k + 1), nullptr, 0, a.wait_limit, a.status) ? 1 : 0;
+            s_go = bounded_wait(a.progress + w, (int)(k + 1), nullptr, 0, nullptr, 0, a.wait_limit, a.status) ? 1 : 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (!s_go) {                                // uniform: the sweep's workgroup gave up, or this wait did
-            if (tid == 0) st_release(a.hdone + w, kGaveUp);
+            if (tid == 0) st_release(mine, kGaveUp);
             return;
         }
         if (k < nbj) {
@@ -280,30 +288,33 @@ __device__ __forceinline__ void gen_far(GenArgs<S> a, int w)
                 const int64_t nlo = i64max(topH, j1 + (k + 1) * r + 1);
                 const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
                 constexpr int U = sizeof(S) * RM <= 256 ? 2 : 1;     // two rows per thread while registers allow
-                far_rows<S, RM, U>(a.SH, a.ST, B, topH, nlo - topH, topT, tdo ? i2 - topT + 1 : 0, i1, m, hsw, sig,
-                                   tid, i1 + 1);
+                if (part == 0)
+                    far_rows<S, RM, U>(a.SH, a.ST, B, topH, nlo - topH, topT, 0, i1, m, hsw, sig, tid, i1 + 1);
+                else if (tdo)
+                    far_rows<S, RM, U>(a.SH, a.ST, B, topH, 0, topT, i2 - topT + 1, i1, m, hsw, sig, tid, i1 + 1);
             }
-            if (!tdo)
+            if (part == 1 && !tdo)
                 for (int e = tid; e < m - 1; e += 256) a.ST[B.idx(i1 + e, i1 - 1)] = zero<S>();
         }
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            st_release(a.hdone + w, (int)(k + 1));
+            st_release(mine, (int)(k + 1));
         }
     }
     __syncthreads();
-    if (tid == 0) st_release(a.hdone + w, kAllDone);
+    if (tid == 0) st_release(mine, kAllDone);
 }
 
 template <class S, int RM>
 __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 {
-    if (blockIdx.x & 1) {                          // odd workgroups: far-row helpers
-        gen_far<S, RM>(a, (int)(blockIdx.x >> 1));
+    const int role = (int)(blockIdx.x % 3);
+    const int w = (int)(blockIdx.x / 3);
+    if (role != 0) {                               // far-row helpers of sweep w: H (1), T (2)
+        gen_far<S, RM>(a, w, role - 1);
         return;
     }
-    const int w = blockIdx.x >> 1;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
     const int64_t j = j1 + w;
@@ -322,14 +333,16 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         if (w > 0) {
             // step k of this sweep follows steps 0..k+2 of the previous sweep
             // (the last of them writes the column this step's near rows
-            // update) and that sweep's far rows of steps 0..k+1 (step k+1's
-            // reach this step's T block, its lazy T column and its near rows;
-            // step k+2's lie right of every column this step touches).
-            // The wait is bounded (see the protocol at the top of the file).
+            // update) and that sweep's far rows of H and T of steps 0..k+1
+            // (step k+1's reach this step's T block, its lazy T column and its
+            // near rows; step k+2's lie right of every column this step
+            // touches).  The wait is bounded (see the protocol at the top of
+            // the file).
             __shared__ int s_go;
             if (tid == 0) {
-                s_go = bounded_wait(a.progress + w - 1, (int)(k + 3), a.hdone + w - 1, (int)(k + 2), a.wait_limit,
-                                    a.status) ? 1 : 0;
+                const int64_t q = j2 - j1 + 1;
+                s_go = bounded_wait(a.progress + w - 1, (int)(k + 3), a.hdone + w - 1, (int)(k + 2),
+                                    a.hdone + q + w - 1, (int)(k + 2), a.wait_limit, a.status) ? 1 : 0;
                 // one acquire per workgroup: it invalidates the caches the
                 // workgroup's waves read through, and the barrier orders their
                 // loads after it

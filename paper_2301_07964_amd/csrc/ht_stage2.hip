@@ -357,7 +357,7 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz, int nbuf =
     g.refl_bytes = g.vbytes * 2 + g.tbytes * 2;
     if (use_mfma(r, esz)) g.refl_bytes += al((size_t)2 * g.kext * kw_of(r) * kw_of(r) * esz);
     g.off_refl = o; o += g.refl_bytes * nbuf;
-    g.off_prog = o; o += al((size_t)2 * q * sizeof(int));          // progress, far-row helpers' progress
+    g.off_prog = o; o += al((size_t)3 * q * sizeof(int));          // progress, far-row helpers' progress (H, T)
     g.total = o;
     return g;
 }
@@ -453,7 +453,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         // 1. scratch band
         { ProfScope ps(prof ? 0 : -1, st);
         hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
-                           (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)(2 * qg));
+                           (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)(3 * qg));
         if ((rc = launch_check("k_band_copy"))) return rc; }
         // 2. generate
         GenArgs<S> ga;
@@ -462,9 +462,9 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         ga.hdone = prog + qg;
         ga.status = status; ga.wait_limit = wait_limit;
         { ProfScope ps(prof ? 1 : -1, st);
-        if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
-        else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
-        else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)(2 * qg)), dim3(256), 0, st, ga);
+        if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)(3 * qg)), dim3(256), 0, st, ga);
+        else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)(3 * qg)), dim3(256), 0, st, ga);
+        else hipLaunchKernelGGL((k_generate<S, 32>), dim3((unsigned)(3 * qg)), dim3(256), 0, st, ga);
         if ((rc = launch_check("k_generate"))) return rc; }
         if (mf) {
             ProfScope ps(prof ? 6 : -1, st);

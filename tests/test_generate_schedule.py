@@ -1,10 +1,11 @@
 """Race check of the generation phase's schedule (CPU model, no GPU).
 
 The generation kernel runs one workgroup per sweep of a group (the step
-chain) and one helper workgroup per sweep (the far rows of each step's eager
-right update, Section 3.2).  Step k of sweep w waits until sweep w-1 has
-finished its steps up to k+2 and its helper the far rows up to step k+1; the
-helper of sweep w runs step k once the sweep's own step k is done.
+chain) and two helper workgroups per sweep (the far rows of each step's eager
+right update, Section 3.2: one for the rows of H, one for those of T).  Step k
+of sweep w waits until sweep w-1 has finished its steps up to k+2 and both its
+helpers the far rows up to step k+1; each helper of sweep w runs step k once
+the sweep's own step k is done.
 
 This test restates, per task, the entries of H and T (and the reflector
 records) that the kernel reads and writes, derives the happens-before order
@@ -29,7 +30,8 @@ def rect(mat, r0, r1, c0, c1):
 
 
 def tasks_of_group(n, r, j1, j2):
-    """{task: (reads, writes)} for the chain ('c', w, k) and helper ('h', w, k) tasks."""
+    """{task: (reads, writes)} for the chain ('c', w, k) and the helper tasks
+    ('hH', w, k) (far rows of H) and ('hT', w, k) (far rows of T)."""
     kext = nblocks(n, r, j1) + 1
     out = {}
     for w in range(j2 - j1 + 1):
@@ -66,24 +68,29 @@ def tasks_of_group(n, r, j1, j2):
                     rd |= cells
                     wr |= cells
             out[("c", w, k)] = (rd, wr)
-            rd, wr = set(), set()
+            rdh, wrh, rdt, wrt = set(), set(), set(), set()
             if k < nbj:
-                rd.add(("VR", w, k))
+                rdh.add(("VR", w, k))
+                rdt.add(("VR", w, k))
                 top_h = max(j1 + 1, j1 + 1 + (k + 1 - d) * r)
                 near = max(top_h, j1 + (k + 1) * r + 1)
                 if top_h <= near - 1:
                     cells = rect("H", top_h, near - 1, i1, i2)
-                    rd |= cells
-                    wr |= cells
+                    rdh |= cells
+                    wrh |= cells
                 if d >= 1:
                     top_t = max(j1 + 1, j1 + 1 + (k - d) * r)
                     cells = rect("T", top_t, i2, i1, i2)
-                    rd |= cells
-                    wr |= cells
+                    rdt |= cells
+                    wrt |= cells
                 else:
-                    wr |= rect("T", i1 + 1, i2, i1, i1)               # exact zeros below the diagonal
-            out[("h", w, k)] = (rd, wr)
+                    wrt |= rect("T", i1 + 1, i2, i1, i1)              # exact zeros below the diagonal
+            out[("hH", w, k)] = (rdh, wrh)
+            out[("hT", w, k)] = (rdt, wrt)
     return out, kext
+
+
+HELPERS = ("hH", "hT")
 
 
 def edges(q, kext, chain_lag=3, helper_lag=2):
@@ -93,12 +100,15 @@ def edges(q, kext, chain_lag=3, helper_lag=2):
         for k in range(kext):
             if k + 1 < kext:
                 e.append((("c", w, k), ("c", w, k + 1)))
-                e.append((("h", w, k), ("h", w, k + 1)))
-            e.append((("c", w, k), ("h", w, k)))
+                for h in HELPERS:
+                    e.append(((h, w, k), (h, w, k + 1)))
+            for h in HELPERS:
+                e.append((("c", w, k), (h, w, k)))
             if w > 0:
                 # progress >= k + chain_lag: steps 0 .. k+chain_lag-1 (all of them at the end)
                 e.append((("c", w - 1, min(k + chain_lag - 1, kext - 1)), ("c", w, k)))
-                e.append((("h", w - 1, min(k + helper_lag - 1, kext - 1)), ("c", w, k)))
+                for h in HELPERS:
+                    e.append(((h, w - 1, min(k + helper_lag - 1, kext - 1)), ("c", w, k)))
     return e
 
 
@@ -125,7 +135,7 @@ def happens_before(tasks, e):
 
 def unblocked_key(t):
     kind, w, k = t
-    return (w, k, 0 if kind == "c" else 1)
+    return (w, k, {"c": 0, "hH": 1, "hT": 2}[kind])
 
 
 def violations(n, r, q, chain_lag=3, helper_lag=2, j1=1):
@@ -161,9 +171,9 @@ def test_later_groups_are_race_free(n, r, q, j1):
 
 def block_of(task):
     """Workgroup index of a task's workgroup in the generate kernel's grid:
-    sweep w is workgroup 2w, its far-row helper 2w + 1."""
+    sweep w is workgroup 3w, its far-row helpers 3w + 1 (H) and 3w + 2 (T)."""
     kind, w, _ = task
-    return 2 * w + (1 if kind == "h" else 0)
+    return 3 * w + {"c": 0, "hH": 1, "hT": 2}[kind]
 
 
 @pytest.mark.parametrize("q", [1, 2, 5, 8, 32])

@@ -20,7 +20,9 @@
 // Work of step (j,k), on the scratch band copy of H and T:
 //   1. lazy left updates: the left reflectors of block k of the earlier sweeps
 //      of the group are applied to the column of H that this step reduces
-//      (jb) and to the column of T that enters its diagonal block (i1+r-1);
+//      (jb) and to the column of T that enters its diagonal block (i1+r-1),
+//      all at once in compact WY form, Q^H x = x - V T^H V^H x (each sweep
+//      adds its column of T while its workgroup factors the T block);
 //      blocks with fewer than two rows still perform these updates;
 //   2. left reflector from H(i1:i2, jb) (xLARFG convention), applied to the
 //      diagonal block T(i1:i2, i1:i2);
@@ -40,7 +42,11 @@
 // in one wavefront, lane l holding row l of the block and lane 32+l row l of
 // the accumulated orthogonal factor, so that a step of the factorisation
 // only broadcasts the pivot row; the eager right updates load a whole row
-// segment before they write any of it back.
+// segment before they write any of it back.  The kernel is also kept small:
+// indices are 32-bit (band offsets stay below 2^31 for every n the library
+// accepts: n * ldb elements), loops over steps are not unrolled, and each
+// piece of work has one copy in the code, so that a workgroup's step loop
+// stays within the instruction cache.
 #pragma once
 #include "ht_common.hpp"
 
@@ -53,6 +59,8 @@ struct GenArgs {
     S *SH, *ST;        // scratch band copies of H and T
     S *VL, *TL;        // left reflectors:  VL[((w*kext)+k)*r + i], TL[w*kext + k]
     S *VR, *TR;        // right reflectors
+    S *TF;             // per (sweep w, block k): column w of the triangular factor of the compact WY
+                       // form of the left reflectors of block k of sweeps j1..j1+w, TF[(w*kext+k)*kMaxR + i]
     int *progress;     // per sweep of the group: blocks whose step chain is finished (-1: gave up)
     int *hdone;        // per sweep: blocks whose far rows of H (hdone[w]) and of T (hdone[q+w]) are finished
     int *status;       // device status word: kStatus* bits, OR-ed in by a wait that gives up
@@ -165,66 +173,34 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
     }
 }
 
-// rows [top, bot] (1-based) of the band copy X, columns i1 .. i1+m-1:
-// X <- X (I - sig w w^H), four lanes per row (each with RM/4 columns of it, the
-// dot product summed over the four), 64 rows per pass of the workgroup; a
-// row's entries are all loaded before any of them is written back.
-template <class S, int RM>
-__device__ inline void near_rows(S *X, const Band &B, int64_t top, int64_t bot, int64_t i1, int m,
-                                 const S *sw, S sig, int tid)
-{
-    constexpr int CP = RM / 4;                     // columns per lane
-    const int64_t cs = B.ldb - 1;                  // stride between columns of one band row
-    const int part = tid & 3, lane = tid & 63;
-    for (int64_t r0 = top; r0 <= bot; r0 += 64) {
-        const int64_t row = r0 + (tid >> 2);
-        const bool on = row <= bot;
-        S *p = X + B.idx(row - 1, i1 - 1);
-        S x[CP];
-        S ds = zero<S>();
-#pragma unroll
-        for (int c = 0; c < CP; ++c) {
-            const int cc = part * CP + c;
-            x[c] = zero<S>();
-            if (on && cc < m) x[c] = p[cc * cs];
-            ds = add(ds, mul(x[c], sw[cc]));
-        }
-        ds = add(ds, shfl_(ds, lane ^ 1));         // every lane takes part in the exchange
-        ds = add(ds, shfl_(ds, lane ^ 2));
-        const S sx = mul(ds, sig);
-#pragma unroll
-        for (int c = 0; c < CP; ++c) {
-            const int cc = part * CP + c;
-            if (on && cc < m) p[cc * cs] = sub(x[c], mul(sx, conj_(sw[cc])));
-        }
-    }
-}
+// 32-bit offsets into the band copy: element (i, c) (0-based) at
+// (i - c + BU) + c * ldb.
+struct Band32 {
+    int BU, ldb;
+    __device__ inline int idx(int i0, int c0) const { return (i0 - c0 + BU) + c0 * ldb; }
+};
 
-// The far rows of one step in one pass: rows [topH, topH+nH) of H, then rows
-// [topT, topT+nT) of T (the first column zeroed from row zrowT on), as one
-// index space over the workgroup; each thread loads U row segments before it
-// writes any, so U rounds of loads are in flight together.
+// The far rows of one step in one pass: rows [top, top+nrow) (1-based) of the
+// band copy X in the block's columns i1 .. i1+m-1, X <- X (I - sig w w^H), the
+// first column of the rows from zrow on written as exact zeros (T's column i1
+// below the diagonal); each thread loads U row segments before it writes any,
+// so U rounds of loads are in flight together.
 template <class S, int RM, int U>
-__device__ __forceinline__ void far_rows(S *XH, S *XT, const Band &B, int64_t topH, int64_t nH, int64_t topT,
-                                         int64_t nT, int64_t i1, int m, const S *sw, S sig, int tid, int64_t zrowT)
+__device__ __forceinline__ void far_rows(S *X, const Band32 &B, int top, int nrow, int i1, int m, const S *sw,
+                                         S sig, int tid, int zrow)
 {
-    const int64_t cs = B.ldb - 1;
-    const int64_t tot = nH + nT;
-    for (int64_t e0 = tid; e0 < tot; e0 += 256 * U) {
+    const int cs = B.ldb - 1;                      // stride between the columns of one band row
+    for (int e0 = tid; e0 < nrow; e0 += 256 * U) {
         S x[U][RM];
-        S *p[U];
-        bool zr[U];
+        int off[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t e = e0 + 256 * u;
-            const bool isH = e < nH;
-            const int64_t row = isH ? topH + e : topT + (e - nH);
-            p[u] = e < tot ? (isH ? XH : XT) + B.idx(row - 1, i1 - 1) : nullptr;
-            zr[u] = !isH && row >= zrowT;
+            const int e = e0 + 256 * u;
+            off[u] = e < nrow ? B.idx(top + e - 1, i1 - 1) : -1;
 #pragma unroll
             for (int c = 0; c < RM; ++c) {
                 x[u][c] = zero<S>();
-                if (p[u] != nullptr && c < m) x[u][c] = p[u][c * cs];
+                if (off[u] >= 0 && c < m) x[u][c] = X[off[u] + c * cs];
             }
         }
 #pragma unroll
@@ -236,9 +212,10 @@ __device__ __forceinline__ void far_rows(S *XH, S *XT, const Band &B, int64_t to
                 d1 = add(d1, mul(x[u][c + 1], sw[c + 1]));
             }
             const S sx = mul(add(d0, d1), sig);
+            const bool zr = top + e0 + 256 * u >= zrow;
 #pragma unroll
             for (int c = 0; c < RM; ++c)
-                if (p[u] != nullptr && c < m) p[u][c * cs] = (c == 0 && zr[u]) ? zero<S>() : sub(x[u][c], mul(sx, conj_(sw[c])));
+                if (off[u] >= 0 && c < m) X[off[u] + c * cs] = (c == 0 && zr) ? zero<S>() : sub(x[u][c], mul(sx, conj_(sw[c])));
         }
     }
 }
@@ -252,21 +229,22 @@ __device__ __forceinline__ void far_rows(S *XH, S *XT, const Band &B, int64_t to
 // workgroup has done the rows of H from j1+(k+1)r+1 on, the only ones its next
 // steps read; the successor sweep waits for all three counters.
 template <class S, int RM>
-__device__ __forceinline__ void gen_far(GenArgs<S> a, int w, int part)
+__device__ __forceinline__ void gen_far(const GenArgs<S> &a, int w, int part)
 {
     const int tid = threadIdx.x;
-    const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
-    const int64_t j = j1 + w, d = j2 - j;
-    const int64_t nbj = nblocks(n, r, j);
-    const Band B = a.band;
-    const int64_t q = j2 - j1 + 1;
+    const int n = (int)a.n, r = (int)a.r, j1 = (int)a.j1, j2 = (int)a.j2, kext = (int)a.kext;
+    const int j = j1 + w, d = j2 - j;
+    const int nbj = (int)nblocks(n, r, j);
+    const Band32 B{(int)a.band.BU, (int)a.band.ldb};
+    const int q = j2 - j1 + 1;
     int *mine = a.hdone + part * q + w;
+    S *X = part == 0 ? a.SH : a.ST;
     __shared__ int s_go;
     __shared__ S hsw[64];
     __shared__ S hsig;
-    for (int64_t k = 0; k < kext; ++k) {
+    for (int k = 0; k < kext; ++k) {
         if (tid == 0) {
-            s_go = bounded_wait(a.progress + w, (int)(k + 1), nullptr, 0, nullptr, 0, a.wait_limit, a.status) ? 1 : 0;
+            s_go = bounded_wait(a.progress + w, k + 1, nullptr, 0, nullptr, 0, a.wait_limit, a.status) ? 1 : 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
@@ -275,35 +253,135 @@ __device__ __forceinline__ void gen_far(GenArgs<S> a, int w, int part)
             return;
         }
         if (k < nbj) {
-            const int64_t i1 = j + k * r + 1;
-            const int64_t i2 = i64min(j + (k + 1) * r, n);
-            const int m = (int)(i2 - i1 + 1);
+            const int i1 = j + k * r + 1;
+            const int i2 = min(j + (k + 1) * r, n);
+            const int m = i2 - i1 + 1;
             if (tid < 64) hsw[tid] = tid < m ? a.VR[(w * kext + k) * r + tid] : zero<S>();
             if (tid == 0) hsig = a.TR[w * kext + k];
             __syncthreads();
             const S sig = hsig;
             const bool tdo = d >= 1 && !iszero(sig);
-            if (!iszero(sig)) {
-                const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
-                const int64_t nlo = i64max(topH, j1 + (k + 1) * r + 1);
-                const int64_t topT = i64max(j1 + 1, j1 + 1 + (k - d) * r);
-                constexpr int U = sizeof(S) * RM <= 256 ? 2 : 1;     // two rows per thread while registers allow
-                if (part == 0)
-                    far_rows<S, RM, U>(a.SH, a.ST, B, topH, nlo - topH, topT, 0, i1, m, hsw, sig, tid, i1 + 1);
-                else if (tdo)
-                    far_rows<S, RM, U>(a.SH, a.ST, B, topH, 0, topT, i2 - topT + 1, i1, m, hsw, sig, tid, i1 + 1);
+            int top = 0, nrow = 0;
+            if (part == 0 && !iszero(sig)) {
+                top = max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
+                nrow = max(top, j1 + (k + 1) * r + 1) - top;
+            } else if (part == 1 && tdo) {
+                top = max(j1 + 1, j1 + 1 + (k - d) * r);
+                nrow = i2 - top + 1;
             }
+            constexpr int U = sizeof(S) * RM <= 256 ? 2 : 1;     // two rows per thread while registers allow
+            if (nrow > 0)
+                far_rows<S, RM, U>(X, B, top, nrow, i1, m, hsw, sig, tid, part == 1 ? i1 + 1 : 0x7fffffff);
             if (part == 1 && !tdo)
                 for (int e = tid; e < m - 1; e += 256) a.ST[B.idx(i1 + e, i1 - 1)] = zero<S>();
         }
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            st_release(mine, (int)(k + 1));
+            st_release(mine, k + 1);
         }
     }
     __syncthreads();
     if (tid == 0) st_release(mine, kAllDone);
+}
+
+// Stage the left reflectors V (v_s at lv[s*r ..]) and the columns of their WY
+// factor T (column s at lT[s*kMaxR ..]) of block kk of the earlier sweeps
+// s < nw into LDS, by NG groups of 32 threads (thread t: group t / 32, entry
+// t % 32; r <= 32): all loads are issued before any is stored, so they are in
+// flight together.
+template <class S, int NG>
+__device__ __forceinline__ void stage_lazy(const GenArgs<S> &a, int kk, int nw, S *lv, S *lT, int t)
+{
+    const int r = (int)a.r, kext = (int)a.kext;
+    const int g = t >> 5, c = t & 31;
+    constexpr int NS = kMaxR / NG;                 // sweeps per group
+    S tv[NS], tt[NS];
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+        const int sw = g + NG * it;
+        tv[it] = zero<S>();
+        tt[it] = zero<S>();
+        if (sw < nw) {
+            if (c < r) tv[it] = a.VL[(sw * kext + kk) * r + c];
+            tt[it] = a.TF[(sw * kext + kk) * kMaxR + c];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NS; ++it) {
+        const int sw = g + NG * it;
+        if (sw < nw) {
+            if (c < r) lv[sw * r + c] = tv[it];
+            lT[sw * kMaxR + c] = tt[it];
+        }
+    }
+}
+
+// Q^H x for Q = G_0 ... G_{nw-1} = I - V T V^H, the compact WY form of the
+// left reflectors of one block of the earlier sweeps (G_i = I - tau_i v_i
+// v_i^H, v_i on rows base+i .. base+i+r-1): x <- x - V (T^H (V^H x)), equal
+// to applying G_0^H, G_1^H, ... in turn.  One wavefront; lane l holds the
+// entry of row base+l.  lv, lT as staged by stage_lazy; ws: 128 values of LDS
+// scratch of this wavefront.
+template <class S>
+__device__ __forceinline__ S lazy_wy(S x, int lane, int nw, int r, const S *lv, const S *lT, S *ws)
+{
+    S *xs = ws, *zs = ws + 64, *us = ws + 96;
+    xs[lane] = x;
+    __builtin_amdgcn_wave_barrier();
+    S z0 = zero<S>(), z1 = zero<S>();              // z_i = v_i^H x   (lane i < nw)
+    if (lane < nw)
+        for (int t = 0; t < r; t += 2) {
+            z0 = add(z0, cmul(lv[lane * r + t], xs[lane + t]));
+            if (t + 1 < r) z1 = add(z1, cmul(lv[lane * r + t + 1], xs[lane + t + 1]));
+        }
+    if (lane < 32) zs[lane] = add(z0, z1);
+    __builtin_amdgcn_wave_barrier();
+    S u0 = zero<S>(), u1 = zero<S>();              // u = T^H z
+    if (lane < nw)
+        for (int jj = 0; jj <= lane; jj += 2) {
+            u0 = add(u0, cmul(lT[lane * kMaxR + jj], zs[jj]));
+            if (jj + 1 <= lane) u1 = add(u1, cmul(lT[lane * kMaxR + jj + 1], zs[jj + 1]));
+        }
+    if (lane < 32) us[lane] = add(u0, u1);
+    __builtin_amdgcn_wave_barrier();
+    S a0 = zero<S>(), a1 = zero<S>();              // V u
+    const int ilo = max(0, lane - r + 1), ihi = min(nw - 1, lane);
+    for (int i = ilo; i <= ihi; i += 2) {
+        a0 = add(a0, mul(lv[i * r + (lane - i)], us[i]));
+        if (i + 1 <= ihi) a1 = add(a1, mul(lv[(i + 1) * r + (lane - i - 1)], us[i + 1]));
+    }
+    return sub(x, add(a0, a1));
+}
+
+// Column nw of the WY factor T for the reflectors of block k of sweeps
+// 0..nw: T(0:nw-1, nw) = -tau T(0:nw-1, 0:nw-1) V^H v, T(nw, nw) = tau
+// (v = sv, the new reflector, on rows base+nw ..; lv, lT as in lazy_wy).
+// One wavefront; written to out[0..nw].
+template <class S>
+__device__ __forceinline__ void wy_column(int lane, int nw, int r, int m, const S *lv, const S *lT, const S *sv,
+                                         S tau, S *ws, S *out)
+{
+    S *zs = ws;
+    S z0 = zero<S>(), z1 = zero<S>();              // z_i = v_i^H v  (lane i < nw); row of v: e = i + t - nw
+    if (lane < nw) {
+        const int tlo = nw - lane, thi = min(r - 1, nw - lane + m - 1);
+        for (int t = tlo; t <= thi; t += 2) {
+            z0 = add(z0, cmul(lv[lane * r + t], sv[lane + t - nw]));
+            if (t + 1 <= thi) z1 = add(z1, cmul(lv[lane * r + t + 1], sv[lane + t + 1 - nw]));
+        }
+    }
+    if (lane < 32) zs[lane] = add(z0, z1);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nw) {
+        S c0 = zero<S>(), c1 = zero<S>();
+        for (int jj = lane; jj < nw; jj += 2) {
+            c0 = add(c0, mul(lT[jj * kMaxR + lane], zs[jj]));
+            if (jj + 1 < nw) c1 = add(c1, mul(lT[(jj + 1) * kMaxR + lane], zs[jj + 1]));
+        }
+        out[lane] = sub(zero<S>(), mul(tau, add(c0, c1)));
+    }
+    if (lane == nw) out[nw] = tau;
 }
 
 template <class S, int RM>
@@ -316,20 +394,28 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         return;
     }
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t n = a.n, r = a.r, j1 = a.j1, j2 = a.j2, kext = a.kext;
-    const int64_t j = j1 + w;
-    const int64_t nbj = nblocks(n, r, j);
-    const Band B = a.band;
+    const int n = (int)a.n, r = (int)a.r, j1 = (int)a.j1, j2 = (int)a.j2, kext = (int)a.kext;
+    const int j = j1 + w;
+    const int nw = w;                              // earlier sweeps of the group
+    const int nbj = (int)nblocks(n, r, j);
+    const int d = j2 - j;
+    const int q = j2 - j1 + 1;
+    const Band32 B{(int)a.band.BU, (int)a.band.ldb};
+    const int cs = B.ldb - 1;                      // stride between the columns of one band row
     S *SH = a.SH, *ST = a.ST;
 
     constexpr int LB = 33;                       // LDS leading dimension of 32x32 blocks
-    __shared__ S sv[64], sw[64], su[64];
+    constexpr int CP = RM / 4;                   // near rows: columns per lane (four lanes per row)
+    __shared__ S sv[64], sw[64];
     __shared__ S blk[32 * LB];
     __shared__ S stau[4];
-    __shared__ S lzv[kMaxR * kMaxR];            // staged lazy reflectors (sweeps j1..j-1, block k)
-    __shared__ S lzt[kMaxR];
+    __shared__ S lzv[2][kMaxR * kMaxR];          // staged lazy reflectors, by block parity
+    __shared__ S lzT[2][kMaxR * kMaxR];          // their WY factor T
+    __shared__ S lws[2][128];                    // per-wavefront scratch of the WY products
+    __shared__ S nrw[64 * RM];                   // the near rows of the current step
+    __shared__ int s_go;
 
-    for (int64_t k = 0; k < kext; ++k) {
+    for (int k = 0; k < kext; ++k) {
         if (w > 0) {
             // step k of this sweep follows steps 0..k+2 of the previous sweep
             // (the last of them writes the column this step's near rows
@@ -338,11 +424,9 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             // near rows; step k+2's lie right of every column this step
             // touches).  The wait is bounded (see the protocol at the top of
             // the file).
-            __shared__ int s_go;
             if (tid == 0) {
-                const int64_t q = j2 - j1 + 1;
-                s_go = bounded_wait(a.progress + w - 1, (int)(k + 3), a.hdone + w - 1, (int)(k + 2),
-                                    a.hdone + q + w - 1, (int)(k + 2), a.wait_limit, a.status) ? 1 : 0;
+                s_go = bounded_wait(a.progress + w - 1, k + 3, a.hdone + w - 1, k + 2, a.hdone + q + w - 1, k + 2,
+                                    a.wait_limit, a.status) ? 1 : 0;
                 // one acquire per workgroup: it invalidates the caches the
                 // workgroup's waves read through, and the barrier orders their
                 // loads after it
@@ -354,67 +438,89 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 return;
             }
         }
-        const int64_t jb = j + i64max(0, (k - 1) * r + 1);
-        const int64_t i1 = j + k * r + 1;
-        const int64_t i2 = i64min(j + (k + 1) * r, n);
-        const int64_t i3 = i64min(j + (k + 2) * r, n);
-        const bool full = k < nbj;
+        const int buf = k & 1;
+        // the lazy reflectors of block 0 are staged here; those of block k+1
+        // are staged during step k (every earlier sweep has finished its step
+        // k+1 by the time this step's wait returns)
+        if (k == 0 && nw > 0) stage_lazy<S, 8>(a, 0, nw, lzv[0], lzT[0], tid);
 
-        // ---- 1. lazy left updates (wave 0: H column jb, wave 1: T column i1+r-1);
-        // the reflectors of block k of the earlier sweeps are first staged in
-        // LDS with one parallel round trip
-        if (j > j1) {
-            const int nw = (int)(j - j1);
-            constexpr int NV = (kMaxR * kMaxR + 255) / 256;      // fixed trip count: loads in flight together
-            S tv[NV];
+        const int jb = j + max(0, (k - 1) * r + 1);
+        const int i1 = j + k * r + 1;
+        const int i2 = min(j + (k + 1) * r, n);
+        const int i3 = min(j + (k + 2) * r, n);
+        const bool full = k < nbj;
+        const int m = full ? i2 - i1 + 1 : 0;            // 2..r
+        // lazy range: rows base..rowmax of the columns jb (H) and i1+r-1 (T)
+        const int base = j1 + k * r + 1;
+        const int rowmax = min(j - 1 + (k + 1) * r, n);
+        const int colT = i1 + r - 1;
+        const bool lazyH = nw > 0 && jb <= n;
+        const bool lazyT = nw > 0 && colT <= n;          // then, for a full block, colT == i2
+        const int cend = full ? i2 : rowmax;             // last row of the two columns this step reads
+        // near rows of the eager right update (this workgroup's part): H rows nr0..i3, columns i1..i2
+        const int topH = max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
+        const int nr0 = max(topH, j1 + (k + 1) * r + 1);
+
+        // ---- A. every load of the step, issued together
+        const int row = base + lane;                     // row of this lane in the two columns
+        S xh = zero<S>(), xt = zero<S>();
+        if (wid == 0 && (lazyH || full) && row <= cend) xh = SH[B.idx(row - 1, jb - 1)];
+        if (wid == 1 && lazyT && row <= cend) xt = ST[B.idx(row - 1, colT - 1)];
+        constexpr int NB = (32 * 32 + 255) / 256;
+        const int mcols = (full && lazyT) ? m - 1 : m;   // the last column comes from wave 1
+        const int boff = B.idx(i1 - 1, i1 - 1);          // T block entry (0, 0); (ii, cc) at boff + ii + cc*cs
+        S tb[NB];
+        int tbi[NB], tbc[NB];
 #pragma unroll
-            for (int it = 0; it < NV; ++it) {
-                const int e = tid + 256 * it;
-                tv[it] = zero<S>();
-                if (e < nw * r) tv[it] = a.VL[((e / (int)r) * kext + k) * r + e % (int)r];
-            }
-            if (tid < nw) lzt[tid] = a.TL[tid * kext + k];
+        for (int it = 0; it < NB; ++it) {
+            const int e = tid + 256 * it;
+            tbc[it] = full ? e / m : 0;                  // block column
+            tbi[it] = e - tbc[it] * m;                   // block row
+            tb[it] = zero<S>();
+            if (full && e < m * mcols) tb[it] = ST[boff + tbi[it] + tbc[it] * cs];
+        }
+        S xn[CP];
+        const int nrow = nr0 + (tid >> 2);
+        const int part = tid & 3;
+        const bool non = full && nrow <= i3;
+        const int noff = B.idx(nrow - 1, i1 - 1);
 #pragma unroll
-            for (int it = 0; it < NV; ++it) {
-                const int e = tid + 256 * it;
-                if (e < nw * r) lzv[e] = tv[it];
-            }
-            __syncthreads();
+        for (int c = 0; c < CP; ++c) {
+            const int cc = part * CP + c;
+            xn[c] = zero<S>();
+            if (non && cc < m) xn[c] = SH[noff + cc * cs];
         }
-        if (wid < 2 && j > j1) {
-            const bool isH = (wid == 0);
-            const int64_t col = isH ? jb : i1 + r - 1;          // 1-based
-            if (col <= n) {
-                S *X = isH ? SH : ST;
-                const int64_t base = j1 + k * r + 1;             // top row of the lazy range
-                const int64_t rowmax = i64min(j - 1 + (k + 1) * r, n);
-                const int64_t row = base + lane;
-                const bool inr = row <= rowmax;
-                S x = inr ? X[B.idx(row - 1, col - 1)] : zero<S>();
-                for (int64_t jh = j1; jh < j; ++jh) {
-                    const int64_t wh = jh - j1;
-                    const S tau = lzt[wh];
-                    if (iszero(tau)) continue;                  // block (jh,k) absent or trivial
-                    const int64_t aa = jh + k * r + 1;
-                    const int64_t bb = i64min(jh + (k + 1) * r, n);
-                    const bool inb = row >= aa && row <= bb;
-                    const S vi = inb ? lzv[wh * r + (row - aa)] : zero<S>();
-                    S s = wave_sum(cmul(vi, x));
-                    s = mul(conj_(tau), s);
-                    if (inb) x = sub(x, mul(s, vi));
-                }
-                if (inr) X[B.idx(row - 1, col - 1)] = x;
-            }
+#pragma unroll
+        for (int it = 0; it < NB; ++it) {
+            const int e = tid + 256 * it;
+            if (full && e < m * mcols) blk[tbc[it] * LB + tbi[it]] = tb[it];
         }
+#pragma unroll
+        for (int c = 0; c < CP; ++c) nrw[(tid >> 2) * RM + part * CP + c] = xn[c];
         __syncthreads();
 
-        if (full) {
-            const int m = (int)(i2 - i1 + 1);               // 2..r
-            // ---- 2. left reflector from H(i1:i2, jb)
-            if (wid == 0) {
-                S x = lane < m ? SH[B.idx(i1 - 1 + lane, jb - 1)] : zero<S>();
+        // ---- B. lazy left updates (wave 0: H column jb, wave 1: T column
+        // i1+r-1) with the left reflectors of block k of the earlier sweeps;
+        // then the left reflector from H(i1:i2, jb) (wave 0)
+        if (wid < 2) {
+            const bool isH = (wid == 0);
+            S x = isH ? xh : xt;
+            if (isH ? lazyH : lazyT) {
+                // rows past the last lazy row (rowmax) take no part: the
+                // reflectors are zero there
+                x = lazy_wy<S>(x, lane, nw, r, lzv[buf], lzT[buf], lws[wid]);
+                // rows above the block go back now; the block's rows are
+                // reduced (H) or take part in the T block (T)
+                const int wlast = full ? i1 - 1 : rowmax;
+                if (row <= wlast) (isH ? SH[B.idx(row - 1, jb - 1)] : ST[B.idx(row - 1, colT - 1)]) = x;
+            }
+            if (!isH && full && lazyT && row >= i1 && row <= i2) blk[(m - 1) * LB + (row - i1)] = x;
+            if (isH && full) {
+                // rows i1..i2 of column jb to lanes 0..m-1
+                S y = shfl_(x, (lane + i1 - base) & 63);
+                if (lane >= m) y = zero<S>();
                 S v, tau, beta;
-                wave_larfg(x, lane, m, v, tau, beta);
+                wave_larfg(y, lane, m, v, tau, beta);
                 if (lane < r) {
                     S vs = lane < m ? v : zero<S>();
                     a.VL[(w * kext + k) * r + lane] = vs;
@@ -428,42 +534,31 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                     SH[B.idx(i1 - 1 + lane, jb - 1)] = zero<S>();
                 }
             }
-            // T block -> LDS
-            {
-                constexpr int NB = (32 * 32 + 255) / 256;
-                S tb[NB];
-#pragma unroll
-                for (int it = 0; it < NB; ++it) {
-                    const int e = tid + 256 * it, ii = e % m, cc = e / m;
-                    tb[it] = zero<S>();
-                    if (e < m * m) tb[it] = ST[B.idx(i1 - 1 + ii, i1 - 1 + cc)];
-                }
-#pragma unroll
-                for (int it = 0; it < NB; ++it) {
-                    const int e = tid + 256 * it, ii = e % m, cc = e / m;
-                    if (e < m * m) blk[cc * LB + ii] = tb[it];
-                }
-            }
-            __syncthreads();
-            {   // apply G^H to the block: 8 lanes per column
+        }
+        __syncthreads();
+
+        if (full) {
+            {   // ---- C. apply G^H to the T block: 8 lanes per column
                 const S tau = stau[0];
                 const int cc = tid >> 3, sub8 = tid & 7;
-                S part = zero<S>();
+                S prt = zero<S>();
                 if (cc < m)
-                    for (int ii = sub8; ii < m; ii += 8) part = add(part, cmul(sv[ii], blk[cc * LB + ii]));
-                S s = group_sum<8>(part);
+                    for (int ii = sub8; ii < m; ii += 8) prt = add(prt, cmul(sv[ii], blk[cc * LB + ii]));
+                S s = group_sum<8>(prt);
                 s = mul(conj_(tau), s);
                 if (cc < m && !iszero(tau))
                     for (int ii = sub8; ii < m; ii += 8) blk[cc * LB + ii] = sub(blk[cc * LB + ii], mul(s, sv[ii]));
             }
             __syncthreads();
-            for (int e = tid; e < m * m; e += 256) {
-                const int ii = e % m, cc = e / m;
-                ST[B.idx(i1 - 1 + ii, i1 - 1 + cc)] = blk[cc * LB + ii];
+            // ---- D. the block goes back to the band (all threads); its RQ
+            // (last row first) on [blk; I] in the registers of wave 0, while
+            // wave 1 forms this sweep's column of the WY factor and waves 2-3
+            // stage the lazy reflectors of the next block
+#pragma unroll
+            for (int it = 0; it < NB; ++it) {
+                const int e = tid + 256 * it;
+                if (e < m * m) ST[boff + tbi[it] + tbc[it] * cs] = blk[tbc[it] * LB + tbi[it]];
             }
-            __syncthreads();
-
-            // ---- 3. RQ of the block (last row first) on [blk; I], in registers
             if (wid == 0) {
                 S x[RM];
 #pragma unroll
@@ -478,8 +573,8 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 S y = shfl_(x[0], 32 + (lane & 31));
                 if (lane >= m) y = zero<S>();
                 unsigned long long mask = __ballot(lane < m && !iszero(y));
-                const int p = mask ? (__ffsll((long long)mask) - 1) : 0;
-                const S yp = bcast(y, p);
+                const int pv = mask ? (__ffsll((long long)mask) - 1) : 0;
+                const S yp = bcast(y, pv);
                 if (!iszero(yp)) {
                     const double ra = 1.0 / sqrt(abs2(yp));
                     if (im(yp) == 0.0) {
@@ -487,7 +582,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                     } else {
                         S ph = mk<S>(re(yp) * ra, -im(yp) * ra);
                         y = mul(y, ph);
-                        if (lane == p) y = mk<S>(re(y), 0.0);
+                        if (lane == pv) y = mk<S>(re(y), 0.0);
                     }
                 }
                 S v, tau, beta;
@@ -495,16 +590,35 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 if (lane < r) a.VR[(w * kext + k) * r + lane] = lane < m ? v : zero<S>();
                 if (lane < RM) sw[lane] = lane < m ? v : zero<S>();
                 if (lane == 0) { a.TR[w * kext + k] = tau; stau[2] = tau; }
+            } else if (wid == 1) {
+                // this sweep's column of the WY factor of block k, for the later sweeps' lazy updates
+                wy_column<S>(lane, nw, r, m, lzv[buf], lzT[buf], sv, stau[0], lws[1], a.TF + (w * kext + k) * kMaxR);
+            } else if (nw > 0 && k + 1 < kext) {
+                stage_lazy<S, 4>(a, k + 1, nw, lzv[buf ^ 1], lzT[buf ^ 1], tid - 128);
             }
             __syncthreads();
 
-            // ---- 4. eager right updates: the rows of H this sweep's next steps
-            // read (from j1+(k+1)r+1 on); the helper workgroup does the rest
+            // ---- E. eager right update of the near rows (from LDS): X <- X (I - sig w w^H),
+            // four lanes per row, each with CP of the row's columns
             const S sig = stau[2];
             if (!iszero(sig)) {
-                const int64_t d = j2 - j;
-                const int64_t topH = i64max(j1 + 1, j1 + 1 + (k + 1 - d) * r);
-                near_rows<S, RM>(SH, B, i64max(topH, j1 + (k + 1) * r + 1), i3, i1, m, sw, sig, tid);
+                S ds = zero<S>();
+#pragma unroll
+                for (int c = 0; c < CP; ++c) {
+                    const int cc = part * CP + c;
+                    xn[c] = nrw[(tid >> 2) * RM + cc];
+                    ds = add(ds, mul(xn[c], sw[cc]));
+                }
+                ds = add(ds, shfl_(ds, lane ^ 1));         // every lane takes part in the exchange
+                ds = add(ds, shfl_(ds, lane ^ 2));
+                const S sx = mul(ds, sig);
+                if (non) {
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) {
+                        const int cc = part * CP + c;
+                        if (cc < m) SH[noff + cc * cs] = sub(xn[c], mul(sx, conj_(sw[cc])));
+                    }
+                }
             }
         } else {
             // absent block: mark both reflectors as identities
@@ -513,13 +627,15 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
                 a.VR[(w * kext + k) * r + tid] = zero<S>();
             }
             if (tid == 0) { a.TL[w * kext + k] = zero<S>(); a.TR[w * kext + k] = zero<S>(); }
+            if (tid <= nw) a.TF[(w * kext + k) * kMaxR + tid] = zero<S>();
+            if (nw > 0 && k + 1 < kext) stage_lazy<S, 8>(a, k + 1, nw, lzv[buf ^ 1], lzT[buf ^ 1], tid);
         }
         // the barrier completes every wave's stores; one agent-scope release
         // (a write-back of the shared cache) then publishes them with the flag
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            st_release(a.progress + w, (int)(k + 1));
+            st_release(a.progress + w, k + 1);
         }
     }
     __syncthreads();

@@ -330,7 +330,7 @@ static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S
 struct Geometry {
     int64_t n, r, q, kext, BU, BL, ldb;
     size_t esz;
-    size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, off_prog, total;
+    size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, fbytes, tfbytes, off_prog, total;
 };
 
 // The matrix-core application path: real and complex, r in {4, 8, 16, 32}.
@@ -354,8 +354,9 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz, int nbuf =
     // window factors of both sides
     g.vbytes = al((size_t)q * g.kext * r * esz);
     g.tbytes = al((size_t)q * g.kext * esz);
-    g.refl_bytes = g.vbytes * 2 + g.tbytes * 2;
-    if (use_mfma(r, esz)) g.refl_bytes += al((size_t)2 * g.kext * kw_of(r) * kw_of(r) * esz);
+    g.fbytes = use_mfma(r, esz) ? al((size_t)2 * g.kext * kw_of(r) * kw_of(r) * esz) : 0;
+    g.tfbytes = al((size_t)q * g.kext * kMaxR * esz);          // WY factors of the lazy left updates
+    g.refl_bytes = g.vbytes * 2 + g.tbytes * 2 + g.fbytes + g.tfbytes;
     g.off_refl = o; o += g.refl_bytes * nbuf;
     g.off_prog = o; o += al((size_t)3 * q * sizeof(int));          // progress, far-row helpers' progress (H, T)
     g.total = o;
@@ -448,6 +449,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         const size_t vbytes = g.vbytes, tbytes = g.tbytes;
         S *VL = (S *)rb, *VR = (S *)(rb + vbytes), *TL = (S *)(rb + 2 * vbytes), *TR = (S *)(rb + 2 * vbytes + tbytes);
         S *F = mf ? (S *)(rb + 2 * vbytes + 2 * tbytes) : nullptr;    // window factors
+        S *TF = (S *)(rb + 2 * vbytes + 2 * tbytes + g.fbytes);        // WY factors of generation
         // the aux stream must be done with this buffer (group grp - kNBuf)
         if (aux && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
         // 1. scratch band
@@ -458,7 +460,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         // 2. generate
         GenArgs<S> ga;
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
-        ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.progress = prog;
+        ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.TF = TF; ga.progress = prog;
         ga.hdone = prog + qg;
         ga.status = status; ga.wait_limit = wait_limit;
         { ProfScope ps(prof ? 1 : -1, st);

@@ -52,8 +52,10 @@ def tasks_of_group(n, r, j1, j2):
                         cells = rect(mat, base, rowmax, col, col)
                         rd |= cells
                         wr |= cells
-                rd |= {("VL", wh, k) for wh in range(w)}
-            wr |= {("VL", w, k), ("VR", w, k)}
+                # the left reflectors (and WY factor columns) of block k of the
+                # earlier sweeps; those of block k+1 are staged during step k
+                rd |= {(rec, wh, kk) for rec in ("VL", "TF") for wh in range(w) for kk in (k, k + 1) if kk < kext}
+            wr |= {("VL", w, k), ("VR", w, k), ("TF", w, k)}
             if k < nbj:
                 cells = rect("H", i1, i2, jb, jb)                     # left reflector's column
                 rd |= cells

@@ -145,27 +145,28 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
         S b[RM];
 #pragma unroll
         for (int c = 0; c <= i; ++c) b[c] = conj_(bcast(x[c], i));
-        // p = sum_{c<i} x_c b_c (per lane) and ||b_{0..i-1}||^2 (uniform)
-        S p0 = zero<S>(), p1 = zero<S>();
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // p = sum_{c<i} x_c b_c (per lane); in the pivot lane i, whose row b
+        // is (conjugated), that sum is ||b_{0..i-1}||^2, real: the norm comes
+        // from there instead of a second sum over the broadcast row
+        S p0 = zero<S>(), p1 = zero<S>(), p2 = zero<S>(), p3 = zero<S>();
 #pragma unroll
         for (int c = 0; c < i; ++c) {
-            if (c & 1) p1 = add(p1, mul(x[c], b[c])); else p0 = add(p0, mul(x[c], b[c]));
             switch (c & 3) {
-                case 0: s0 += abs2(b[c]); break;
-                case 1: s1 += abs2(b[c]); break;
-                case 2: s2 += abs2(b[c]); break;
-                default: s3 += abs2(b[c]); break;
+                case 0: p0 = add(p0, mul(x[c], b[c])); break;
+                case 1: p1 = add(p1, mul(x[c], b[c])); break;
+                case 2: p2 = add(p2, mul(x[c], b[c])); break;
+                default: p3 = add(p3, mul(x[c], b[c])); break;
             }
         }
+        const S pp = add(add(p0, p1), add(p2, p3));
         const S alpha = b[i];
-        const double ss = (s0 + s1) + (s2 + s3);
+        const double ss = bcast(re(pp), i);
         if (ss == 0.0 && im(alpha) == 0.0) continue;              // tau = 0: identity
         S tau, sc;                                               // u_c = b_c sc (c < i), u_i = 1
         double bb;
         larfg_core(alpha, ss, tau, bb, sc);
         // s = (x_i + sum_{c<i} x_c u_c) tau;  x_c -= s conj(u_c) = (s conj(sc)) conj(b_c)
-        const S sv = mul(add(x[i], mul(add(p0, p1), sc)), tau);
+        const S sv = mul(add(x[i], mul(pp, sc)), tau);
         const S t = mul(sv, conj_(sc));
 #pragma unroll
         for (int c = 0; c < i; ++c) x[c] = sub(x[c], mul(t, conj_(b[c])));

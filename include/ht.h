@@ -167,9 +167,10 @@ int64_t ht_get_knob(int knob);
 /*
  * ht_stage2_batched -- `count` independent stage-two reductions (pencils of
  * uneven n and r, each as ht_stage2 defines it) in ONE persistent launch:
- * every workgroup takes whole pencils from a device-side queue and chases
- * their bulges with the unblocked algorithm of the appendix (Section 3.1),
- * each reflector applied at once to its full range.  The reflectors are
+ * workgroups (or single wavefronts, per ht_batched_set_tuning) take whole
+ * pencils from device-side queues, longest first, and chase their bulges
+ * with the unblocked algorithm of the appendix (Section 3.1), each reflector
+ * applied at once to its full range.  The reflectors are
  * those of ht_stage2, so the results agree with it up to rounding.  Meant
  * for many small pencils (n up to about a thousand), where the latency of
  * the sweep steps, not flops, bounds the time.
@@ -189,6 +190,21 @@ int ht_stage2_batched_z(int64_t count, void *const *H, void *const *T,
                         void *const *Q, void *const *Z, const int64_t *n,
                         const int64_t *r, const int64_t *ld, const int64_t *q,
                         void *stream);
+
+/*
+ * ht_batched_set_tuning -- the table that decides, per pencil, how
+ * ht_stage2_batched(_z) reduces it: by a workgroup of 256 threads or by a
+ * single wavefront of 64 (four pencils per workgroup at a time).  Entry e
+ * applies to pencils with n <= n_max[e] and min(r, n-1) == r[e] (r[e] = 0:
+ * any r); the first matching entry decides; threads[e] is 64 or 256.
+ * Without a matching entry a pencil with n <= 128 takes a wavefront.  The
+ * arrays are host arrays, copied before return; entries = 0 clears the table.
+ * Process-wide; calls already enqueued are not affected.  Meant for the
+ * autotuner's table (paper_2301_07964_amd/autotune.py).
+ * Errors: -1 entries < 0, -2 NULL array, -3 r < 0, -4 threads not 64 or 256.
+ */
+int ht_batched_set_tuning(int64_t entries, const int64_t *n_max, const int64_t *r,
+                          const int64_t *threads);
 
 /*
  * ht_rhess -- stage one: reduce a dense pencil (A, B) to r-Hessenberg-

@@ -83,8 +83,41 @@ def lib(with_torch: bool = True):
     L.ht_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), _PI, _int]
     L.ht_batched_completion_ms.argtypes = [ctypes.POINTER(ctypes.c_double), _i64]
     L.ht_batched_completion_ms.restype = _int
+    L.ht_batched_set_tuning.argtypes = [_i64, _PI, _PI, _PI]
+    L.ht_batched_set_tuning.restype = _int
     _lib = L
+    _apply_batched_table(L)
     return L
+
+
+def _apply_batched_table(L):
+    """Hand the autotuner's batched table (autotune_table.json, key "batched":
+    [n_max, r, threads] entries) to the library, if there is one."""
+    import json
+    path = os.path.join(_HERE, "autotune_table.json")
+    if not os.path.exists(path):
+        return
+    with open(path) as f:
+        ent = json.load(f).get("batched", [])
+    if ent:
+        _set_tuning(L, ent)
+
+
+def _set_tuning(L, entries):
+    k = len(entries)
+    nm, rr, th = (_i64 * max(k, 1))(), (_i64 * max(k, 1))(), (_i64 * max(k, 1))()
+    for i, (a, b, c) in enumerate(entries):
+        nm[i], rr[i], th[i] = int(a), int(b), int(c)
+    rc = L.ht_batched_set_tuning(k, ctypes.cast(nm, _PI), ctypes.cast(rr, _PI), ctypes.cast(th, _PI))
+    if rc != 0:
+        raise ValueError(f"ht_batched_set_tuning: {rc}")
+
+
+def set_batched_tuning(entries):
+    """Set the batched path's table: entries (n_max, r, threads), threads 64
+    (one wavefront per pencil) or 256 (a workgroup); r = 0 matches any r; the
+    first match decides; [] restores the built-in rule."""
+    _set_tuning(lib(), list(entries))
 
 
 EXPORTS = (
@@ -93,7 +126,7 @@ EXPORTS = (
     "ht_stage2_batched_z", "ht_rhess", "ht_rhess_z", "ht_rhess_p", "ht_rhess_z_p", "ht_rhess_default_p",
     "ht_workspace_bytes", "ht_rhess_workspace_bytes", "ht_reserve_workspace",
     "ht_release_workspace", "ht_default_q", "ht_strerror", "ht_version", "ht_last_error_message",
-    "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms",
+    "ht_profile_enable", "ht_profile_read", "ht_batched_completion_ms", "ht_batched_set_tuning",
 )
 
 # knob ids of include/ht.h

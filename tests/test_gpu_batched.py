@@ -204,3 +204,46 @@ def test_reserved_workspace_serves_later_calls():
     assert np.all(np.tril(An, -(r + 1)) == 0) and np.all(np.tril(Bn, -1) == 0)
     with pytest.raises(ht.HTError):
         ht.reserve_workspace(-1, st)
+
+
+@pytest.mark.parametrize("threads", [64, 256])
+def test_batched_parity_both_modes_up_to_512(threads):
+    """Oracle parity of the batched launch on a sample that covers the whole
+    batched workload range (n up to 512, r in {4, 8, 16}), with every pencil
+    forced onto one wavefront (64) or one workgroup (256) through the tuning
+    table; entry by entry within 1e-9."""
+    from oracle import oracle as O
+    ht = _ht()
+    rng = np.random.default_rng(31)
+    pencils = []
+    for i, (n, r) in enumerate([(512, 4), (500, 16), (451, 8), (384, 16), (300, 4), (257, 8), (200, 16), (129, 4),
+                                (96, 8), (64, 8), (40, 4), (33, 4)]):
+        H, T = inputs.rht_pencil(n, r, 700 + i)
+        pencils.append((H, T, r))
+    old = []
+    ht.set_batched_tuning([(100000, 0, threads)])
+    try:
+        got = _run_batched(pencils)
+    finally:
+        ht.set_batched_tuning(old)
+        ht._apply_batched_table(ht.lib())
+    for (H, T, r), g in zip(pencils, got):
+        ref = O.stage2(H, T, r)
+        errs = [rel(a, b) for a, b in zip(g, ref[:4])]
+        print(f"[batched {threads}] n={H.shape[0]} r={r} errs={max(errs):.2e}", flush=True)
+        assert max(errs) <= TOL, (threads, H.shape[0], r, errs)
+        assert np.all(np.tril(g[0], -2) == 0) and np.all(np.tril(g[1], -1) == 0)
+
+
+def test_batched_tuning_arguments():
+    ht = _ht()
+    L = ht.lib()
+    import ctypes
+    a = (ctypes.c_int64 * 1)(100)
+    b = (ctypes.c_int64 * 1)(4)
+    c = (ctypes.c_int64 * 1)(128)
+    P = ctypes.POINTER(ctypes.c_int64)
+    assert L.ht_batched_set_tuning(-1, None, None, None) == -1
+    assert L.ht_batched_set_tuning(1, None, None, None) == -2
+    assert L.ht_batched_set_tuning(1, ctypes.cast(a, P), ctypes.cast(b, P), ctypes.cast(c, P)) == -4
+    ht._apply_batched_table(L)

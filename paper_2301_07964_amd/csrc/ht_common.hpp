@@ -52,18 +52,48 @@ __host__ __device__ inline zd recip(zd z) {
     double e = c / d, f = d + c * e; return mk<zd>(e / f, -1.0 / f);
 }
 
+// Square root and reciprocal of positive normal doubles with a short chain of
+// dependent operations (the reflector scalars sit on the critical path of
+// the generate phase): the hardware estimates refined by Newton's method --
+// for the square root Goldschmidt's coupled iteration on g ~ sqrt(s),
+// h ~ 1/(2 sqrt(s)), two steps and a final residual correction; for the
+// reciprocal two Newton-Raphson steps y <- y + y (1 - d y).  Accurate to about
+// an ulp, not correctly rounded; the inputs here are O(1) (entries of the
+// pencil), far from overflow, underflow and zero.
+__device__ __forceinline__ double sqrt_nr(double s)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, s);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ double rcp_nr(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
 // xLARFG scalars for a non-trivial reflector (ss = ||x||^2 > 0 or alpha not
 // real): beta = -sign(Re alpha) sqrt(|alpha|^2 + ss), tau = (beta - alpha) /
-// beta and sc = 1 / (alpha - beta), with a single division: 1 / beta and
+// beta and sc = 1 / (alpha - beta), with a single reciprocal: 1 / beta and
 // 1 / |alpha - beta|^2 both come from q = 1 / (beta |alpha - beta|^2).
 // |Re(alpha - beta)| = |Re alpha| + |beta| >= |beta| > 0, so q is finite.
 template <class S>
 __device__ __forceinline__ void larfg_core(S alpha, double ss, S &tau, double &beta, S &sc)
 {
-    const double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt(abs2(alpha) + ss);
+    const double b = -(re(alpha) >= 0.0 ? 1.0 : -1.0) * sqrt_nr(abs2(alpha) + ss);
     const S amb = sub(alpha, mk<S>(b, 0.0));
     const double n2 = abs2(amb);
-    const double q = 1.0 / (b * n2);
+    const double q = rcp_nr(b * n2);
     const double rb = n2 * q;                     // 1 / beta
     tau = mk<S>((b - re(alpha)) * rb, -im(alpha) * rb);
     sc = scal(conj_(amb), b * q);                 // conj(amb) / |amb|^2

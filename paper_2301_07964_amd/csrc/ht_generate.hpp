@@ -148,17 +148,13 @@ __device__ inline void rq_rows(S (&x)[RM], int m)
         // p = sum_{c<i} x_c b_c (per lane); in the pivot lane i, whose row b
         // is (conjugated), that sum is ||b_{0..i-1}||^2, real: the norm comes
         // from there instead of a second sum over the broadcast row
-        S p0 = zero<S>(), p1 = zero<S>(), p2 = zero<S>(), p3 = zero<S>();
+        // eight partial sums: the sum is on the critical path of the step
+        S pa[8];
 #pragma unroll
-        for (int c = 0; c < i; ++c) {
-            switch (c & 3) {
-                case 0: p0 = add(p0, mul(x[c], b[c])); break;
-                case 1: p1 = add(p1, mul(x[c], b[c])); break;
-                case 2: p2 = add(p2, mul(x[c], b[c])); break;
-                default: p3 = add(p3, mul(x[c], b[c])); break;
-            }
-        }
-        const S pp = add(add(p0, p1), add(p2, p3));
+        for (int e = 0; e < 8; ++e) pa[e] = zero<S>();
+#pragma unroll
+        for (int c = 0; c < i; ++c) pa[c & 7] = add(pa[c & 7], mul(x[c], b[c]));
+        const S pp = add(add(add(pa[0], pa[1]), add(pa[2], pa[3])), add(add(pa[4], pa[5]), add(pa[6], pa[7])));
         const S alpha = b[i];
         const double ss = bcast(re(pp), i);
         if (ss == 0.0 && im(alpha) == 0.0) continue;              // tau = 0: identity

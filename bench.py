@@ -456,8 +456,6 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--lookahead", type=int, default=None, choices=(0, 1),
-                    help="overlap generation with the previous group's updates (library knob); default: the library's")
     ap.add_argument("--workload", choices=("single", "batched", "serving", "stage1", "copy"), default="single",
                     help="single: one n x n pencil (headline); batched: 2048 small pencils in one launch; "
                          "serving: the complex128 request loop; stage1: dense -> r-HT; copy: counter calibration")
@@ -493,8 +491,6 @@ def main():
     H, T = inputs.rht_pencil(n, r, args.seed)
     Hd0, Td0 = ht.colmajor(H, dev), ht.colmajor(T, dev)
     q = args.q if args.q else ht.default_q(n, r)
-    if args.lookahead is not None:
-        ht.set_knob(ht.KNOB_LOOKAHEAD, args.lookahead)
     # one working set, restored from the pristine copies before every step
     # (outside the timed region)
     Hd, Td = torch.empty_like(Hd0), torch.empty_like(Td0)

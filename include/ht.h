@@ -155,12 +155,9 @@ int ht_stream_status(void *stream);
  *     makes every wait give up at once (used to test the failure path).
  *   HT_KNOB_UPDATE_TILE_ROWS [0]: tiles of 16 rows per wavefront in the
  *     matrix-core right updates; 0 = automatic (2 for n >= 8192), 1 or 2.
- *   HT_KNOB_LOOKAHEAD [0]: 1 = overlap the generation of each group of sweeps
- *     with the delayed updates of the previous group (Section 3.3).
  */
 #define HT_KNOB_WAIT_POLLS 1
 #define HT_KNOB_UPDATE_TILE_ROWS 2
-#define HT_KNOB_LOOKAHEAD 3
 int ht_set_knob(int knob, int64_t value);
 int64_t ht_get_knob(int knob);
 

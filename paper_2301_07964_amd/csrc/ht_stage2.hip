@@ -687,7 +687,6 @@ int ht_set_knob(int knob, int64_t value)
     switch (knob) {
     case HT_KNOB_WAIT_POLLS: if (value < 0) return -2; break;
     case HT_KNOB_UPDATE_TILE_ROWS: if (value < 0 || value > 2) return -2; break;
-    case HT_KNOB_LOOKAHEAD: if (value < 0 || value > 1) return -2; break;
     default: break;
     }
     ht::knobs()[knob - 1].store(value, std::memory_order_relaxed);

@@ -130,7 +130,7 @@ EXPORTS = (
 )
 
 # knob ids of include/ht.h
-KNOB_WAIT_POLLS, KNOB_UPDATE_TILE_ROWS = 1, 2
+KNOB_WAIT_POLLS, KNOB_UPDATE_TILE_ROWS, KNOB_LOOKAHEAD = 1, 2, 3
 
 
 def set_knob(knob: int, value: int):

@@ -65,6 +65,10 @@ struct GenArgs {
     int *hdone;        // per sweep: blocks whose far rows of H (hdone[w]) and of T (hdone[q+w]) are finished
     int *status;       // device status word: kStatus* bits, OR-ed in by a wait that gives up
     int64_t wait_limit;  // polls before a wait gives up (0: give up without polling)
+    const int *flags;  // lookahead: per tile of 16 columns, raised by the previous group's left pass once the
+                       // tile's scratch band is written; nullptr: the band is complete at launch
+    int flag_need;     // value of a flag whose tile is ready
+    int ntiles;        // number of tiles (ceil(n / 16))
 };
 
 // status bits of the device status word
@@ -104,6 +108,29 @@ __device__ inline bool bounded_wait(const int *c1, int need1, const int *c2, int
         const int v1 = ld_relaxed(c1), v2 = c2 ? ld_relaxed(c2) : need2, v3 = c3 ? ld_relaxed(c3) : need3;
         if (v1 == kGaveUp || v2 == kGaveUp || v3 == kGaveUp) return false;
         if (v1 >= need1 && v2 >= need2 && v3 >= need3) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Bounded wait of one wavefront (lane = lane index) until the tiles t0..tneed
+// of the scratch band are ready (flags[t] >= need).  Lane l polls tile t0+l;
+// every poll takes the whole run of ready tiles that starts at t0, so one
+// wait usually covers many later steps.  Returns the first tile not known to
+// be ready (> tneed), or -1 after `limit` polls (timeout bit OR-ed into
+// *status).  Like bounded_wait, the caller issues the acquire fence.
+__device__ inline int tiles_wait(const int *flags, int t0, int tneed, int ntiles, int need, int lane, int64_t limit,
+                                 int *status)
+{
+    for (int64_t polls = 0;; ++polls) {
+        if (polls >= limit) {
+            if (lane == 0) __hip_atomic_fetch_or(status, kStatusWaitTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        const int t = t0 + lane;
+        const bool ok = t >= ntiles || ld_relaxed(flags + t) >= need;
+        const unsigned long long nr = ~__ballot(ok);
+        t0 = min(ntiles, t0 + (nr ? __ffsll((long long)nr) - 1 : 64));
+        if (t0 > tneed) return t0;
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -411,8 +438,30 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
     __shared__ S lws[2][128];                    // per-wavefront scratch of the WY products
     __shared__ S nrw[64 * RM];                   // the near rows of the current step
     __shared__ int s_go;
+    int tready = (j1 - 1) >> 4;                  // lookahead: tiles of the band below this one are ready
 
     for (int k = 0; k < kext; ++k) {
+        if (w == 0 && a.flags) {
+            // the first sweep reads columns j1 .. min(j1+(k+1)r, n) up to step k;
+            // later sweeps read no column before this sweep has read it
+            const int tneed = (min(j + (k + 1) * r, n) - 1) >> 4;
+            if (tready <= tneed) {
+                if (wid == 0) {
+                    const int t = tiles_wait(a.flags, tready, tneed, a.ntiles, a.flag_need, lane, a.wait_limit,
+                                             a.status);
+                    if (lane == 0) {
+                        s_go = t;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
+                __syncthreads();
+                tready = s_go;
+                if (tready < 0) {
+                    if (tid == 0) st_release(a.progress + w, kGaveUp);
+                    return;
+                }
+            }
+        }
         if (w > 0) {
             // step k of this sweep follows steps 0..k+2 of the previous sweep
             // (the last of them writes the column this step's near rows

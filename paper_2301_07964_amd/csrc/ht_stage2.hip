@@ -8,7 +8,12 @@
 //   2. generate phase (ht_generate.hpp): reflectors of the q sweeps;
 //   3. application phase (ht_update.hpp): right updates of H, T, Z and Q,
 //      then left updates of H and T.
-// All work is enqueued on the caller's stream.
+// The Q and Z updates of a group run on an auxiliary stream, beside the next
+// group's work on the caller's stream.  With lookahead (real, r = 32) the left
+// pass of group g and then group g's Q and Z updates run on a second stream,
+// while group g+1's generation runs on the caller's stream, reading each tile
+// of its scratch band once the left pass has written it.  Every call joins
+// its streams into the caller's stream before it returns.
 #include "ht_common.hpp"
 #include "ht_generate.hpp"
 #include "ht_update.hpp"
@@ -74,9 +79,10 @@ struct ProfScope {
 template <class S>
 __global__ __launch_bounds__(256) void k_band_copy(const S *__restrict__ H, const S *__restrict__ T, int64_t ld,
                                                    S *SH, S *ST, Band B, int64_t n, int64_t c0,
-                                                   int *progress, int nprog)
+                                                   int *progress, int nprog, int *flags, int nflags)
 {
     if (blockIdx.x == 0 && (int)threadIdx.x < nprog) progress[threadIdx.x] = 0;
+    if (threadIdx.x == 0 && (int)blockIdx.x < nflags) flags[blockIdx.x] = 0;
     const int64_t c = c0 + blockIdx.x;
     if (c >= n) return;
     const int64_t ilo = i64max(0, c - B.BU), ihi = i64min(n - 1, c + B.BL);
@@ -95,48 +101,27 @@ __global__ __launch_bounds__(256) void k_zero_lower(S *X, int64_t ld, int64_t n,
     for (int64_t i = c + off + 1 + threadIdx.x; i < n; i += blockDim.x) X[i + c * ld] = zero<S>();
 }
 
-// Exact zeros of the structure after the last sweep j2 of a group.  In exact
-// arithmetic the delayed updates leave zeros there; in floating point they
-// leave rounding residue that the unblocked algorithm never has (it writes the
-// annihilated entries as zeros and never touches the others).  If the residue
-// stayed, the next group's scratch copy would inherit it and the generate
-// phase's restricted update ranges would treat it inconsistently, and the
-// mismatch feeds back from group to group.  Below the diagonal, T keeps only
-// the blocks I(j2,k) x I(j2,k) without their first column; H keeps the first
-// subdiagonal for columns <= j2, and for later columns the r-band plus the
-// fill blocks I(j2,k+1) x (I(j2,k) minus its first column).
+// Exact zeros of the structure after the last sweep j2 of a group (the rule
+// of CleanCol), rows c+1 .. c+depth of the columns c >= c0.
 template <class S>
 __global__ __launch_bounds__(256) void k_clean(S *H, S *T, int64_t ld, int64_t n, int64_t r, int64_t j2,
                                                int64_t c0, int64_t depth)
 {
     const int64_t c = c0 + blockIdx.x;              // 0-based column
     if (c >= n) return;
-    const int64_t c1 = c + 1;                       // 1-based column
-    const int64_t nb2 = nblocks(n, r, j2);
-    // block of sweep j2 that contains column c1 (if any)
-    int64_t kb = -1, a = 0, b = 0;
-    if (c1 >= j2 + 1) {
-        kb = (c1 - j2 - 1) / r;
-        if (kb >= nb2) kb = -1;
-        else { a = j2 + kb * r + 1; b = i64min(a + r - 1, n); }
+    const CleanCol cc(c, r, n, j2);
+    const int64_t rend = i64min(n, c + 1 + depth);   // 1-based last row examined
+    for (int64_t i1b = c + 2 + threadIdx.x; i1b <= rend; i1b += blockDim.x) {
+        if (!cc.keepT(i1b)) T[(i1b - 1) + c * ld] = zero<S>();
+        if (!cc.keepH(i1b)) H[(i1b - 1) + c * ld] = zero<S>();
     }
-    const int64_t rend = i64min(n, c1 + depth);      // 1-based last row examined
-    for (int64_t i1b = c1 + 1 + threadIdx.x; i1b <= rend; i1b += blockDim.x) {
-        // T
-        bool keepT = (kb >= 0 && c1 > a && i1b <= b);
-        if (!keepT) T[(i1b - 1) + c * ld] = zero<S>();
-        // H
-        bool keepH;
-        if (c1 <= j2) keepH = (i1b <= c1 + 1);
-        else {
-            keepH = (i1b <= c1 + r);
-            if (!keepH && kb >= 0 && c1 > a) {
-                const int64_t a2 = a + r, b2 = i64min(a2 + r - 1, n);
-                keepH = (a2 <= n && i1b >= a2 && i1b <= b2);
-            }
-        }
-        if (!keepH) H[(i1b - 1) + c * ld] = zero<S>();
-    }
+}
+
+// Progress counters of the generate phase to zero (when no band copy runs
+// before it)
+__global__ void k_zero_ints(int *p, int cnt)
+{
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) p[i] = 0;
 }
 
 template <class S>
@@ -150,6 +135,23 @@ static int zero_lower(S *X, int64_t ld, int64_t n, int64_t off, hipStream_t st, 
 
 inline int64_t default_q(int64_t n, int64_t r) { (void)n; return r; }
 
+// A short pause on the left stream before each left pass of the lookahead
+// schedule.  The left pass and the next group's generation become ready
+// together (when the right pass ends); the generation's workgroups each need a
+// whole compute unit (their register use allows one wavefront per SIMD), and
+// the left pass's small workgroups, if dispatched first, would take every
+// unit.  The pause lets the generation be dispatched first (measured at
+// n = 16384, r = 32: 5.30 s a reduction with a pause of 10 us to 80 us,
+// 5.61 s without).  Bounded by the device's constant-rate clock.
+constexpr int kLaDelayUs = 10;
+__global__ void k_delay(int64_t ticks)
+{
+    if (threadIdx.x == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (wall_clock64() - t0 < (uint64_t)ticks) __builtin_amdgcn_s_sleep(8);
+    }
+}
+
 // Reflector buffers: the Q/Z updates of group g run on an auxiliary stream
 // while the caller's stream goes on with group g+1, so consecutive groups use
 // different buffers.
@@ -159,6 +161,12 @@ constexpr int kNBuf = 2;
 struct AuxCtx {
     hipStream_t aux = nullptr;
     hipEvent_t gen[kNBuf] = {}, qz[kNBuf] = {}, join = nullptr;
+    // lookahead: the left pass of group g, then the Q and Z updates of group
+    // g, run on `left` once the right pass (event rdone) is done; the caller's
+    // stream waits for the left pass (ldone) before the right pass of group g+1
+    hipStream_t left = nullptr;
+    hipEvent_t rdone = nullptr, ldone = nullptr;
+    int64_t delay_ticks = 0;      // kLaDelayUs in ticks of the device's constant-rate clock
     bool ok = false;
 };
 static std::mutex g_aux_mu;
@@ -177,6 +185,12 @@ static AuxCtx *aux_ctx(hipStream_t st)
         if (hipEventCreateWithFlags(&c.qz[b], hipEventDisableTiming) != hipSuccess) return nullptr;
     }
     if (hipEventCreateWithFlags(&c.join, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipStreamCreateWithFlags(&c.left, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c.rdone, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c.ldone, hipEventDisableTiming) != hipSuccess) return nullptr;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    c.delay_ticks = (int64_t)khz * kLaDelayUs / 1000;
     c.ok = true;
     return &c;
 }
@@ -330,7 +344,7 @@ static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S
 struct Geometry {
     int64_t n, r, q, kext, BU, BL, ldb;
     size_t esz;
-    size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, fbytes, tfbytes, off_prog, total;
+    size_t off_SH, off_ST, off_refl, refl_bytes, vbytes, tbytes, fbytes, tfbytes, off_prog, off_flags, total;
 };
 
 // The matrix-core application path: real and complex, r in {4, 8, 16, 32}.
@@ -359,6 +373,7 @@ static Geometry geometry(int64_t n, int64_t r, int64_t q, size_t esz, int nbuf =
     g.refl_bytes = g.vbytes * 2 + g.tbytes * 2 + g.fbytes + g.tfbytes;
     g.off_refl = o; o += g.refl_bytes * nbuf;
     g.off_prog = o; o += al((size_t)3 * q * sizeof(int));          // progress, far-row helpers' progress (H, T)
+    g.off_flags = o; o += al((size_t)((n + 15) / 16) * sizeof(int));  // lookahead: tiles of the band ready
     g.total = o;
     return g;
 }
@@ -431,12 +446,19 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     const Band B{g.BU, g.BL, g.ldb};
     const int64_t rr = re_;
     const bool qz = (Q != nullptr) || (Z != nullptr);
-    const bool aux = qz && !fx;                      // Q and Z on the auxiliary stream
-    AuxCtx *ax = aux ? aux_ctx(st) : nullptr;
-    if (aux && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
+    const bool mf = use_mfma(rr, sizeof(S));
+    // lookahead: the left pass of group g (with the exact zeros and the next
+    // group's band copy in its per-tile epilogue), then group g's Q and Z
+    // updates, on a second stream; the generation of group g+1 waits for the
+    // tiles of the band it reads
+    const bool la = !fx && mf && sizeof(S) == 8 && rr == 32 && knob(HT_KNOB_LOOKAHEAD) != 0;
+    const bool aux = qz && !fx && !la;               // otherwise Q and Z on the auxiliary stream
+    AuxCtx *ax = (aux || la) ? aux_ctx(st) : nullptr;
+    if ((aux || la) && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
     const bool prof = !fx;                           // kernel timing creates events: not for fixed scratch
     const int64_t np = (n + 63) / 64;
-    const bool mf = use_mfma(rr, sizeof(S));
+    int *flags = la ? (int *)(ws + g.off_flags) : nullptr;
+    const int ntiles = (int)((n + 15) / 16);
 
     int64_t grp = 0;
     for (int64_t j1 = 1; j1 <= jlast; j1 += q, ++grp) {
@@ -450,19 +472,30 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         S *VL = (S *)rb, *VR = (S *)(rb + vbytes), *TL = (S *)(rb + 2 * vbytes), *TR = (S *)(rb + 2 * vbytes + tbytes);
         S *F = mf ? (S *)(rb + 2 * vbytes + 2 * tbytes) : nullptr;    // window factors
         S *TF = (S *)(rb + 2 * vbytes + 2 * tbytes + g.fbytes);        // WY factors of generation
-        // the aux stream must be done with this buffer (group grp - kNBuf)
-        if (aux && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess) return HT_ERR_HIP;
-        // 1. scratch band
-        { ProfScope ps(prof ? 0 : -1, st);
-        hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
-                           (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)(3 * qg));
-        if ((rc = launch_check("k_band_copy"))) return rc; }
+        // the Q and Z updates of group grp - kNBuf must be done with this buffer
+        if ((aux || (la && qz)) && grp >= kNBuf && hipStreamWaitEvent(st, ax->qz[buf], 0) != hipSuccess)
+            return HT_ERR_HIP;
+        // 1. scratch band (lookahead: from the second group on, written by the
+        // previous group's left pass)
+        if (!la || grp == 0) {
+            ProfScope ps(prof ? 0 : -1, st);
+            hipLaunchKernelGGL(k_band_copy<S>, dim3((unsigned)(n - (j1 - 1))), dim3(256), 0, st,
+                               (const S *)H, (const S *)T, ld, SH, ST, B, n, j1 - 1, prog, (int)(3 * qg),
+                               flags, la ? ntiles : 0);
+            if ((rc = launch_check("k_band_copy"))) return rc;
+        } else {
+            hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(256), 0, st, prog, (int)(3 * qg));
+            if ((rc = launch_check("k_zero_ints"))) return rc;
+        }
         // 2. generate
-        GenArgs<S> ga;
+        GenArgs<S> ga{};
         ga.n = n; ga.r = rr; ga.j1 = j1; ga.j2 = j2; ga.kext = kext; ga.band = B;
         ga.SH = SH; ga.ST = ST; ga.VL = VL; ga.TL = TL; ga.VR = VR; ga.TR = TR; ga.TF = TF; ga.progress = prog;
         ga.hdone = prog + qg;
         ga.status = status; ga.wait_limit = wait_limit;
+        ga.flags = la && grp > 0 ? flags : nullptr;
+        ga.flag_need = (int)(2 * grp);
+        ga.ntiles = ntiles;
         { ProfScope ps(prof ? 1 : -1, st);
         if (rr <= 8) hipLaunchKernelGGL((k_generate<S, 8>), dim3((unsigned)(3 * qg)), dim3(256), 0, st, ga);
         else if (rr <= 16) hipLaunchKernelGGL((k_generate<S, 16>), dim3((unsigned)(3 * qg)), dim3(256), 0, st, ga);
@@ -476,50 +509,80 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
                 if ((rc = launch_form_factors_z(rr, qg, kmax, kext, VL, TL, VR, TR, (double *)F, st))) return rc;
             }
         }
-        UpdArgs<S> ua;
+        UpdArgs<S> ua{};
         ua.n = n; ua.r = rr; ua.q = qg; ua.j1 = j1; ua.kmax = kmax; ua.kext = kext;
         ua.VL = VL; ua.TL = TL; ua.VR = VR; ua.TR = TR;
         int nj = 0;
         int64_t tot = 0;
-        auto addjob = [&](S *X, int side, int64_t lim) {
+        auto addjob = [&](S *X, int side, int64_t lim, int mat) {
             if (!X) return;
             ua.job[nj].X = X; ua.job[nj].ld = ld; ua.job[nj].lim = lim; ua.job[nj].npanels = np; ua.job[nj].side = side;
+            ua.job[nj].mat = mat;
             ++nj; tot += np;
         };
         // 3a. Q and Z (right updates) on the auxiliary stream (fixed scratch:
-        // on the caller's stream)
-        if (qz) {
+        // on the caller's stream; lookahead: after the left pass, below)
+        if (qz && !la) {
             hipStream_t qs = st;
             if (aux) {
                 if (hipEventRecord(ax->gen[buf], st) != hipSuccess) return HT_ERR_HIP;
                 if (hipStreamWaitEvent(ax->aux, ax->gen[buf], 0) != hipSuccess) return HT_ERR_HIP;
                 qs = ax->aux;
             }
-            addjob(Z, 1, -1);
-            addjob(Q, 0, -1);
+            addjob(Z, 1, -1, 2);
+            addjob(Q, 0, -1, 2);
             ua.njobs = nj;
             { ProfScope ps(prof ? 5 : -1, qs);
             if ((rc = launch_pass<S>(true, ua, tot, F, qs))) return rc; }
             if (aux && hipEventRecord(ax->qz[buf], ax->aux) != hipSuccess) return HT_ERR_HIP;
         }
         // 3b. H and T: right updates, then left updates, then the exact zeros
+        // (lookahead: the right pass waits for the previous group's left pass)
+        if (la && grp > 0 && hipStreamWaitEvent(st, ax->ldone, 0) != hipSuccess) return HT_ERR_HIP;
         nj = 0; tot = 0;
-        addjob(H, 1, (q + 2) * rr);
-        addjob(T, 1, (q + 1) * rr);
+        addjob(H, 1, (q + 2) * rr, 0);
+        addjob(T, 1, (q + 1) * rr, 1);
         ua.njobs = nj;
         { ProfScope ps(prof ? 2 : -1, st);
         if ((rc = launch_pass<S>(true, ua, tot, F, st))) return rc; }
         nj = 0; tot = 0;
-        addjob(H, 0, (q + 1) * rr);
-        addjob(T, 0, (q + 1) * rr);
+        addjob(H, 0, (q + 1) * rr, 0);
+        addjob(T, 0, (q + 1) * rr, 1);
         ua.njobs = nj;
+        const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr), depth = (q + 4) * rr;
+        if (la) {
+            if (hipEventRecord(ax->rdone, st) != hipSuccess) return HT_ERR_HIP;
+            if (hipStreamWaitEvent(ax->left, ax->rdone, 0) != hipSuccess) return HT_ERR_HIP;
+            hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, ax->left, ax->delay_ticks);
+            if ((rc = launch_check("k_delay"))) return rc;
+            LeftEpi<S> &e = ua.epi;
+            e.SH = SH; e.ST = ST; e.band = B;
+            e.c0 = j2 < jlast ? j2 : n;              // the next group's first column j2+1 (1-based)
+            e.j2 = j2; e.cc0 = cc0; e.depth = depth; e.flags = flags;
+            { ProfScope ps(prof ? 3 : -1, ax->left);
+            if ((rc = launch_pass<S>(false, ua, tot, F, ax->left))) return rc; }
+            if (hipEventRecord(ax->ldone, ax->left) != hipSuccess) return HT_ERR_HIP;
+            if (qz) {
+                ua.epi.flags = nullptr;
+                nj = 0; tot = 0;
+                addjob(Z, 1, -1, 2);
+                addjob(Q, 0, -1, 2);
+                ua.njobs = nj;
+                { ProfScope ps(prof ? 5 : -1, ax->left);
+                if ((rc = launch_pass<S>(true, ua, tot, F, ax->left))) return rc; }
+                if (hipEventRecord(ax->qz[buf], ax->left) != hipSuccess) return HT_ERR_HIP;
+            }
+            continue;
+        }
         { ProfScope ps(prof ? 3 : -1, st);
         if ((rc = launch_pass<S>(false, ua, tot, F, st))) return rc; }
         { ProfScope ps(prof ? 4 : -1, st);
-        const int64_t cc0 = i64max(0, j1 - 1 - (q + 2) * rr);
-        hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0,
-                           (q + 4) * rr);
+        hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0, depth);
         if ((rc = launch_check("k_clean"))) return rc; }
+    }
+    if (la) {    // join the left stream
+        if (hipEventRecord(ax->ldone, ax->left) != hipSuccess) return HT_ERR_HIP;
+        if (hipStreamWaitEvent(st, ax->ldone, 0) != hipSuccess) return HT_ERR_HIP;
     }
     if (aux) {   // join the auxiliary stream
         if (hipEventRecord(ax->join, ax->aux) != hipSuccess) return HT_ERR_HIP;
@@ -687,6 +750,7 @@ int ht_set_knob(int knob, int64_t value)
     switch (knob) {
     case HT_KNOB_WAIT_POLLS: if (value < 0) return -2; break;
     case HT_KNOB_UPDATE_TILE_ROWS: if (value < 0 || value > 2) return -2; break;
+    case HT_KNOB_LOOKAHEAD: if (value < 0 || value > 1) return -2; break;
     default: break;
     }
     ht::knobs()[knob - 1].store(value, std::memory_order_relaxed);

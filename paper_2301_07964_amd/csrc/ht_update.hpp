@@ -30,6 +30,59 @@ struct UpdJob {
     int64_t lim;       // < 0: every window; else window k active iff p0 < hi_k+1+lim (right) / c0+64 > lo_k-lim (left)
     int64_t npanels;
     int side;          // 0: left reflectors (VL/TL), 1: right reflectors (VR/TR)
+    int mat;           // 0: H, 1: T, 2: Q or Z (selects the rule of the exact zeros and the scratch band)
+};
+
+// Exact zeros of the structure after the last sweep j2 of a group, for one
+// column (0-based c).  In exact arithmetic the delayed updates leave zeros
+// there; in floating point they leave rounding residue that the unblocked
+// algorithm never has (it writes the annihilated entries as zeros and never
+// touches the others).  If the residue stayed, the next group's scratch copy
+// would inherit it and the generate phase's restricted update ranges would
+// treat it inconsistently, and the mismatch feeds back from group to group.
+// Below the diagonal, T keeps only the blocks I(j2,k) x I(j2,k) without their
+// first column; H keeps the first subdiagonal for columns <= j2, and for later
+// columns the r-band plus the fill blocks I(j2,k+1) x (I(j2,k) minus its first
+// column).  Rows are 1-based in keepH / keepT.
+struct CleanCol {
+    int64_t c1, r, n, j2, a, b;
+    bool inblk;        // c1 lies in a block of sweep j2 and is not its first column
+    __host__ __device__ CleanCol(int64_t c, int64_t r_, int64_t n_, int64_t j2_) : c1(c + 1), r(r_), n(n_), j2(j2_)
+    {
+        a = 0; b = 0; inblk = false;
+        if (c1 >= j2 + 1) {
+            const int64_t kb = (c1 - j2 - 1) / r;
+            if (kb < nblocks(n, r, j2)) {
+                a = j2 + kb * r + 1;
+                b = i64min(a + r - 1, n);
+                inblk = c1 > a;
+            }
+        }
+    }
+    __host__ __device__ bool keepT(int64_t i1b) const { return inblk && i1b <= b; }
+    __host__ __device__ bool keepH(int64_t i1b) const
+    {
+        if (c1 <= j2) return i1b <= c1 + 1;
+        if (i1b <= c1 + r) return true;
+        const int64_t a2 = a + r, b2 = i64min(a2 + r - 1, n);
+        return inblk && a2 <= n && i1b >= a2 && i1b <= b2;
+    }
+};
+
+// Epilogue of the left pass for lookahead (the next group's generation runs
+// while this pass is still going): once a tile of columns has taken its last
+// window, it writes the group's exact zeros in those columns, copies their
+// band into the next group's scratch band and adds one to the tile's flag
+// (agent-scope release), so that after group g every flag reads 2 (g + 1):
+// one for the H tile, one for the T tile.
+template <class S>
+struct LeftEpi {
+    S *SH, *ST;            // scratch band of the next group
+    Band band;
+    int64_t c0;            // first column (0-based) of the next group's band; >= n: nothing to copy
+    int64_t j2;            // last sweep of this group (1-based)
+    int64_t cc0, depth;    // exact zeros in columns >= cc0, rows c+1 .. c+depth (0-based)
+    int *flags;            // per tile of 16 columns; nullptr: no epilogue
 };
 
 template <class S>
@@ -38,7 +91,37 @@ struct UpdArgs {
     const S *VL, *TL, *VR, *TR;
     UpdJob<S> job[4];
     int njobs;
+    LeftEpi<S> epi;
 };
+
+// The epilogue for columns p0 .. p0+ncol-1 of job J, by nthr threads (thread
+// t); the caller has made the tile's updates of X visible to every thread.
+template <class S>
+__device__ inline void left_epilogue(const UpdArgs<S> &a, const UpdJob<S> &J, int64_t p0, int ncol, int t, int nthr)
+{
+    const LeftEpi<S> &e = a.epi;
+    const int64_t n = a.n;
+    S *X = J.X;
+    S *SB = J.mat == 1 ? e.ST : e.SH;
+    const Band B = e.band;
+    for (int cl = 0; cl < ncol; ++cl) {
+        const int64_t c = p0 + cl;
+        if (c >= n) break;
+        const CleanCol cc(c, a.r, n, e.j2);
+        const bool cln = c >= e.cc0;
+        const int64_t zlast = cln ? i64min(n - 1, c + e.depth) : c;    // last row of the exact zeros
+        const bool cpy = c >= e.c0;
+        const int64_t blo = i64max(0, c - B.BU), bhi = i64min(n - 1, c + B.BL);
+        const int64_t rlo = cpy ? blo : c + 1, rhi = cpy ? i64max(bhi, zlast) : zlast;
+        for (int64_t i = rlo + t; i <= rhi; i += nthr) {
+            const bool z = i > c && i <= zlast && !(J.mat == 1 ? cc.keepT(i + 1) : cc.keepH(i + 1));
+            S v = zero<S>();
+            if (z) X[i + c * J.ld] = v;
+            else if (cpy && i <= bhi) v = X[i + c * J.ld];
+            if (cpy && i <= bhi) SB[B.idx(i, c)] = v;
+        }
+    }
+}
 
 // ring slot of local index c (< 2r) of window k (streaming from k = kmax-1
 // downwards): windows advance by r and the ring has 2r slots, so only the

@@ -398,8 +398,12 @@ __global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, con
     UpdJob<double> J = a.job[0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
-    const int64_t bi = (int64_t)(blockIdx.x / a.njobs);
-    const int64_t b = LEFT ? J.npanels - 1 - bi : bi;
+    const int64_t bi = (int64_t)(blockIdx.x / a.njobs), n_ = a.n;
+    // left: rightmost tiles (most windows) first, unless the next group's
+    // generation waits for the tiles' epilogues: then from the first tile it
+    // reads rightwards, the tiles left of it last
+    const bool epi = LEFT && a.epi.flags != nullptr;
+    const int64_t b = !LEFT ? bi : !epi ? J.npanels - 1 - bi : (bi + (a.epi.c0 < n_ ? a.epi.c0 / NL : 0)) % J.npanels;
     if (b < 0 || b >= J.npanels) return;
     const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
     const int W = (int)(q + R - 1);
@@ -416,99 +420,112 @@ __global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, con
             if (klast >= kmax) return;
         } else {
             while (kfirst >= 0 && !(p0 + NL > j1 + kfirst * R - J.lim)) --kfirst;
-            if (kfirst < 0) return;
+            if (kfirst < 0 && !epi) return;
         }
     }
-    // element (tile line j, window index c) of the window starting at lo
-    auto at = [&](int j, int64_t lo, int c, bool &ok) -> int64_t {
-        const int64_t fixed = p0 + j, idx = lo + c;
-        ok = fixed < n && idx < n;
-        return LEFT ? idx + fixed * ld : fixed + idx * ld;
-    };
-    // element e of a whole window (NL x 64) or of the new indices (NL x R),
-    // the contiguous dimension fastest
-    auto wmap = [&](int e, int &j, int &c) { if (LEFT) { c = e & 63; j = e >> 6; } else { j = e % NL; c = e / NL; } };
-    auto nmap = [&](int e, int &j, int &c) { if (LEFT) { c = e % R; j = e / R; } else { j = e % NL; c = e / NL; } };
-    {
-        const int64_t lo = j1 + kfirst * R;
+    if (kfirst >= klast) {                         // the tile takes part in at least one window
+        // element (tile line j, window index c) of the window starting at lo
+        auto at = [&](int j, int64_t lo, int c, bool &ok) -> int64_t {
+            const int64_t fixed = p0 + j, idx = lo + c;
+            ok = fixed < n && idx < n;
+            return LEFT ? idx + fixed * ld : fixed + idx * ld;
+        };
+        // element e of a whole window (NL x 64) or of the new indices (NL x R),
+        // the contiguous dimension fastest
+        auto wmap = [&](int e, int &j, int &c) { if (LEFT) { c = e & 63; j = e >> 6; } else { j = e % NL; c = e / NL; } };
+        auto nmap = [&](int e, int &j, int &c) { if (LEFT) { c = e % R; j = e / R; } else { j = e % NL; c = e / NL; } };
+        {
+            const int64_t lo = j1 + kfirst * R;
 #pragma unroll
-        for (int i = 0; i < 4 * TC; ++i) {
-            int j, c;
-            wmap(tid + 256 * i, j, c);
-            bool ok;
-            const int64_t ad = at(j, lo, c, ok);
-            buf[0][j * LT + c] = (ok && c < W) ? X[ad] : 0.0;
-            buf[1][j * LT + c] = 0.0;              // indices >= W of the other buffer stay zero
-        }
-    }
-    double pre[2 * TC];
-    auto load_new = [&](int64_t kn) {
-        const int64_t lo = j1 + kn * R;
-#pragma unroll
-        for (int i = 0; i < 2 * TC; ++i) {
-            int j, c;
-            nmap(tid + 256 * i, j, c);
-            bool ok;
-            const int64_t ad = at(j, lo, c, ok);
-            pre[i] = ok ? X[ad] : 0.0;
-        }
-    };
-    if (kfirst > klast) load_new(kfirst - 1);
-    double af[KK];
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) af[kk] = Fs[kfirst * (KW * KW) + (wv * KK + kk) * 64 + lane];
-    __syncthreads();
-    int cur = 0;
-    for (int64_t k = kfirst; k >= klast; --k) {
-        const int64_t lo = j1 + k * R;
-        const bool more = k > klast;
-        double afn[KK];
-        if (more) {
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk) afn[kk] = Fs[(k - 1) * (KW * KW) + (wv * KK + kk) * 64 + lane];
-        }
-        f64x4 acc[TC];
-#pragma unroll
-        for (int t = 0; t < TC; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-            for (int t = 0; t < TC; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], buf[cur][(16 * t + li) * LT + 4 * kk + g], acc[t],
-                                                              0, 0, 0);
-        const int f0 = more ? (int)(q - 1) : 0;
-        const int nxt = cur ^ 1;
-        double *ow = ob[k & 1];
-#pragma unroll
-        for (int t = 0; t < TC; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = 16 * wv + 4 * v + g, j = 16 * t + li;
-                if (c >= f0 && c < W) ow[j * LT + c] = acc[t][v];
-                if (more && c < q - 1) buf[nxt][j * LT + c + R] = acc[t][v];    // index c + R of window k-1
+            for (int i = 0; i < 4 * TC; ++i) {
+                int j, c;
+                wmap(tid + 256 * i, j, c);
+                bool ok;
+                const int64_t ad = at(j, lo, c, ok);
+                buf[0][j * LT + c] = (ok && c < W) ? X[ad] : 0.0;
+                buf[1][j * LT + c] = 0.0;              // indices >= W of the other buffer stay zero
             }
-        if (more) {
+        }
+        double pre[2 * TC];
+        auto load_new = [&](int64_t kn) {
+            const int64_t lo = j1 + kn * R;
 #pragma unroll
             for (int i = 0; i < 2 * TC; ++i) {
                 int j, c;
                 nmap(tid + 256 * i, j, c);
-                buf[nxt][j * LT + c] = pre[i];
+                bool ok;
+                const int64_t ad = at(j, lo, c, ok);
+                pre[i] = ok ? X[ad] : 0.0;
             }
-        }
+        };
+        if (kfirst > klast) load_new(kfirst - 1);
+        double af[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) af[kk] = Fs[kfirst * (KW * KW) + (wv * KK + kk) * 64 + lane];
         __syncthreads();
+        int cur = 0;
+        for (int64_t k = kfirst; k >= klast; --k) {
+            const int64_t lo = j1 + k * R;
+            const bool more = k > klast;
+            double afn[KK];
+            if (more) {
 #pragma unroll
-        for (int i = 0; i < 4 * TC; ++i) {
-            int j, c;
-            wmap(tid + 256 * i, j, c);
-            bool ok;
-            const int64_t ad = at(j, lo, c, ok);
-            if (ok && c >= f0 && c < W) X[ad] = ow[j * LT + c];
+                for (int kk = 0; kk < KK; ++kk) afn[kk] = Fs[(k - 1) * (KW * KW) + (wv * KK + kk) * 64 + lane];
+            }
+            f64x4 acc[TC];
+#pragma unroll
+            for (int t = 0; t < TC; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+                for (int t = 0; t < TC; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], buf[cur][(16 * t + li) * LT + 4 * kk + g], acc[t],
+                                                                  0, 0, 0);
+            const int f0 = more ? (int)(q - 1) : 0;
+            const int nxt = cur ^ 1;
+            double *ow = ob[k & 1];
+#pragma unroll
+            for (int t = 0; t < TC; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 16 * wv + 4 * v + g, j = 16 * t + li;
+                    if (c >= f0 && c < W) ow[j * LT + c] = acc[t][v];
+                    if (more && c < q - 1) buf[nxt][j * LT + c + R] = acc[t][v];    // index c + R of window k-1
+                }
+            if (more) {
+#pragma unroll
+                for (int i = 0; i < 2 * TC; ++i) {
+                    int j, c;
+                    nmap(tid + 256 * i, j, c);
+                    buf[nxt][j * LT + c] = pre[i];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4 * TC; ++i) {
+                int j, c;
+                wmap(tid + 256 * i, j, c);
+                bool ok;
+                const int64_t ad = at(j, lo, c, ok);
+                if (ok && c >= f0 && c < W) X[ad] = ow[j * LT + c];
+            }
+            if (!more) break;
+            if (k - 1 > klast) load_new(k - 2);
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) af[kk] = afn[kk];
+            cur = nxt;
         }
-        if (!more) break;
-        if (k - 1 > klast) load_new(k - 2);
+    }
+    if (epi) {
+        __syncthreads();                           // the tile's last window is in memory
+        left_epilogue<double>(a, J, p0, NL, tid, 256);
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) af[kk] = afn[kk];
-        cur = nxt;
+            for (int t = 0; t < TC; ++t)
+                __hip_atomic_fetch_add(a.epi.flags + b * TC + t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 

@@ -16,12 +16,13 @@ namespace ht {
 
 // ------------------------------------------------------------------ knobs
 // Process-wide settings (ht_set_knob / ht_get_knob).  Index = HT_KNOB_* - 1.
-constexpr int kNumKnobs = 2;
+constexpr int kNumKnobs = 3;
 inline std::atomic<int64_t> *knobs()
 {
     static std::atomic<int64_t> k[kNumKnobs] = {
         {int64_t(1) << 22},   // HT_KNOB_WAIT_POLLS: polls before a device-side wait gives up
         {0},                  // HT_KNOB_UPDATE_TILE_ROWS: 0 automatic, 1 or 2 tiles of 16 rows per wavefront
+        {1},                  // HT_KNOB_LOOKAHEAD: generation of group g+1 overlaps the left updates of group g
     };
     return k;
 }

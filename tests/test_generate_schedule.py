@@ -195,3 +195,51 @@ def test_model_detects_a_missing_wait():
     assert violations(61, 4, 4, helper_lag=1)
     # and a chain stagger of two leaves the predecessor's step k+2 unordered
     assert violations(61, 4, 4, chain_lag=2)
+
+
+# ------------------------------------------------------------- lookahead
+
+def lookahead_violations(n, r, q, j1=1, tw=16, ahead=1):
+    """With lookahead the scratch band of a group is written tile by tile (tw
+    columns each) by the previous group's left pass, while this group's
+    generation runs.  The first sweep's step k waits until the tiles of
+    columns j1 .. min(j1+(k+ahead)r, n) are written (the kernel: ahead = 1).
+    Returns the (tile, task) pairs where a task touches a column of H or T
+    before that column's tile is ordered before it."""
+    j2 = min(j1 + q - 1, n - 2)
+    qq = j2 - j1 + 1
+    tasks, kext = tasks_of_group(n, r, j1, j2)
+    e = edges(qq, kext)
+    ntiles = (n + tw - 1) // tw
+    alltasks = dict(tasks)
+    for t in range(ntiles):
+        alltasks[("L", t, 0)] = (set(), set())
+    for k in range(kext):
+        tneed = (min(j1 + (k + ahead) * r, n) - 1) // tw
+        for t in range((j1 - 1) // tw, tneed + 1):
+            e.append((("L", t, 0), ("c", 0, k)))
+    reach = happens_before(alltasks, e)
+    bad = set()
+    for task, (rd, wr) in tasks.items():
+        for mat, _, c in rd | wr:
+            if mat in ("H", "T"):
+                tile = ("L", (c - 1) // tw, 0)
+                if task not in reach[tile]:
+                    bad.add((tile, task))
+    return bad
+
+
+@pytest.mark.parametrize("n,r,q,j1", [(61, 4, 4, 1), (61, 4, 4, 9), (90, 8, 8, 17), (75, 5, 3, 4), (70, 16, 16, 1),
+                                      (50, 3, 3, 44)])
+@pytest.mark.parametrize("tw", [1, 3, 16])
+def test_lookahead_tiles_cover_every_access(n, r, q, j1, tw):
+    """Every entry of the scratch band that any task of the group reads or
+    writes lies in a tile that the first sweep waited for before a step that
+    happens before that task (later sweeps and helpers inherit the order
+    through their own waits)."""
+    assert lookahead_violations(n, r, q, j1, tw) == set()
+
+
+def test_lookahead_model_detects_a_short_wait():
+    # waiting only for the columns of the steps before k misses step k's block
+    assert lookahead_violations(61, 4, 4, tw=1, ahead=0)

@@ -347,6 +347,77 @@ def test_knob_arguments():
     assert L.ht_set_knob(ht.KNOB_WAIT_POLLS, -1) == -2
     assert L.ht_set_knob(ht.KNOB_UPDATE_TILE_ROWS, 3) == -2
     assert L.ht_get_knob(ht.KNOB_UPDATE_TILE_ROWS) == 0
+    assert L.ht_set_knob(ht.KNOB_LOOKAHEAD, 2) == -2 and L.ht_set_knob(ht.KNOB_LOOKAHEAD, -1) == -2
+    assert L.ht_get_knob(ht.KNOB_LOOKAHEAD) == 1
+
+
+# ------------------------------------------------------------- lookahead
+
+def _with_lookahead(on, fn):
+    ht = _ht()
+    old = ht.set_knob(ht.KNOB_LOOKAHEAD, 1 if on else 0)
+    try:
+        return fn()
+    finally:
+        ht.set_knob(ht.KNOB_LOOKAHEAD, old)
+
+
+@pytest.mark.parametrize("n,q,jmax,acc", [(900, 32, -1, True), (2100, 32, -1, True), (1500, 7, -1, True),
+                                          (1200, 32, 70, True), (1000, 32, -1, False), (33, 32, -1, True),
+                                          (4096, 32, 96, True)])
+def test_lookahead_is_bitwise_the_sequential_order(n, q, jmax, acc):
+    """Lookahead (Section 3.3; real r = 32): the generation of group g+1 runs
+    while the left updates of group g are in progress, reading each tile of
+    its scratch band once that tile's epilogue has written it.  Every kernel
+    does the same arithmetic on the same values as in the sequential order,
+    so the outputs are bitwise equal; n not a multiple of 16, groups cut by
+    jmax, q < r, no accumulation and a single group are covered."""
+    ht = _ht()
+    r = 32
+    H, T = inputs.rht_pencil(n, r, 17)
+    print(f"[lookahead] n={n} r={r} q={q} jmax={jmax} acc={acc}", flush=True)
+
+    def run():
+        Hd, Td = ht.colmajor(H), ht.colmajor(T)
+        Qd = ht.colmajor(np.eye(n)) if acc else None
+        Zd = ht.colmajor(np.eye(n)) if acc else None
+        ht.stage2(Hd, Td, min(r, n - 1), Qd, Zd, q=min(q, n - 1), jmax=jmax)
+        torch.cuda.synchronize()
+        assert ht.stream_status() == 0
+        return [ht.to_numpy(x) for x in (Hd, Td, Qd, Zd) if x is not None]
+
+    on = _with_lookahead(True, run)
+    off = _with_lookahead(False, run)
+    for a, b in zip(on, off):
+        assert np.array_equal(a, b)
+
+
+def test_lookahead_parity_vs_oracle():
+    """The lookahead path (the default at r = 32) against the oracle, with a
+    group count that leaves a short last group."""
+    H, T = inputs.rht_pencil(1111, 32, 23)
+    check_parity(H, T, 32)
+
+
+def test_lookahead_wait_give_up_is_reported():
+    """The lookahead wait of the generate phase is bounded like the others:
+    with a wait limit of 0 it gives up, every kernel exits, the status word
+    reports HT_ERR_TIMEOUT, and the next call is correct."""
+    ht = _ht()
+    n, r = 700, 32
+    H, T = inputs.rht_pencil(n, r, 8)
+    assert ht.stream_status() == 0
+    old = ht.set_knob(ht.KNOB_WAIT_POLLS, 0)
+    try:
+        Hd, Td = ht.colmajor(H), ht.colmajor(T)
+        ht.stage2(Hd, Td, r, ht.colmajor(np.eye(n)), ht.colmajor(np.eye(n)))
+        torch.cuda.synchronize()
+    finally:
+        ht.set_knob(ht.KNOB_WAIT_POLLS, old)
+    assert ht.stream_status() == 5
+    assert ht.stream_status() == 0
+    check_parity(H, T, r)
+    assert ht.stream_status() == 0
 
 
 # ------------------------------------------------------------- singular T

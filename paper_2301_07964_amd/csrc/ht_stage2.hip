@@ -9,11 +9,11 @@
 //   3. application phase (ht_update.hpp): right updates of H, T, Z and Q,
 //      then left updates of H and T.
 // The Q and Z updates of a group run on an auxiliary stream, beside the next
-// group's work on the caller's stream.  With lookahead (real, r = 32) the left
-// pass of group g and then group g's Q and Z updates run on a second stream,
-// while group g+1's generation runs on the caller's stream, reading each tile
-// of its scratch band once the left pass has written it.  Every call joins
-// its streams into the caller's stream before it returns.
+// group's work on the caller's stream.  With lookahead (real, r in {4, 8, 16,
+// 32}) the left pass of group g and then group g's Q and Z updates run on a
+// second stream, while group g+1's generation runs on the caller's stream,
+// reading each tile of its scratch band once the left pass has written it.
+// Every call joins its streams into the caller's stream before it returns.
 #include "ht_common.hpp"
 #include "ht_generate.hpp"
 #include "ht_update.hpp"
@@ -451,7 +451,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     // group's band copy in its per-tile epilogue), then group g's Q and Z
     // updates, on a second stream; the generation of group g+1 waits for the
     // tiles of the band it reads
-    const bool la = !fx && mf && sizeof(S) == 8 && rr == 32 && knob(HT_KNOB_LOOKAHEAD) != 0;
+    const bool la = !fx && mf && sizeof(S) == 8 && knob(HT_KNOB_LOOKAHEAD) != 0;
     const bool aux = qz && !fx && !la;               // otherwise Q and Z on the auxiliary stream
     AuxCtx *ax = (aux || la) ? aux_ctx(st) : nullptr;
     if ((aux || la) && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }

@@ -100,6 +100,10 @@ __global__ __launch_bounds__(256) void k_update_mfma(UpdArgs<double> a, const do
     for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
     if (b >= J.npanels) return;
     const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
+    // left with lookahead epilogues: from the first tile the next group's
+    // generation reads rightwards, the tiles left of it last
+    const bool epi = LEFT && a.epi.flags != nullptr;
+    if (epi) b = (b + (a.epi.c0 < n ? a.epi.c0 / (16 * TRW) : 0)) % J.npanels;
     const int64_t W = q + R - 1;
     const int g = lane >> 4, li = lane & 15;
     const int64_t p0 = b * (16 * TRW);              // first row (right) / column (left) of the tiles
@@ -115,83 +119,100 @@ __global__ __launch_bounds__(256) void k_update_mfma(UpdArgs<double> a, const do
             if (klast >= kmax) return;
         } else {
             while (kfirst >= 0 && !(p0 + 16 * TRW > j1 + kfirst * R - J.lim)) --kfirst;
-            if (kfirst < 0) return;
+            if (kfirst < 0 && !epi) return;
         }
     }
-    // element (tile t, window index c) of window starting at lo
-    auto addr = [&](int t, int64_t lo, int c, bool &ok) -> int64_t {
-        const int64_t fixed = p0 + 16 * t + li, idx = lo + c;
-        ok = fixed < n && idx < n;
-        return LEFT ? idx + fixed * ld : fixed + idx * ld;
-    };
+    if (kfirst >= klast) {                         // the tiles take part in at least one window
+        // element (tile t, window index c) of window starting at lo
+        auto addr = [&](int t, int64_t lo, int c, bool &ok) -> int64_t {
+            const int64_t fixed = p0 + 16 * t + li, idx = lo + c;
+            ok = fixed < n && idx < n;
+            return LEFT ? idx + fixed * ld : fixed + idx * ld;
+        };
 
-    double xb[TRW][KK];
-    {
-        const int64_t lo = j1 + kfirst * R;
+        double xb[TRW][KK];
+        {
+            const int64_t lo = j1 + kfirst * R;
 #pragma unroll
-        for (int t = 0; t < TRW; ++t)
+            for (int t = 0; t < TRW; ++t)
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) {
-                const int c = 4 * kk + g;
-                bool ok;
-                const int64_t ad = addr(t, lo, c, ok);
-                double v = 0.0;
-                if (ok && c < W) v = X[ad];
-                xb[t][kk] = v;
-            }
-    }
-    for (int64_t k = kfirst; k >= klast; --k) {
-        const int64_t lo = j1 + k * R;
-        const double *Fk = Fs + k * (KW * KW);
-        f64x4 acc[TRW][MB];
-#pragma unroll
-        for (int t = 0; t < TRW; ++t)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            double af[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) af[mb] = Fk[(mb * KK + kk) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int t = 0; t < TRW; ++t)
-                    acc[t][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], xb[t][kk], acc[t][mb], 0, 0, 0);
-        }
-        // finished indices go back to HBM
-        const int64_t f0 = (k == klast) ? 0 : q - 1;
-#pragma unroll
-        for (int t = 0; t < TRW; ++t)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c = 16 * mb + 4 * v + g;
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int c = 4 * kk + g;
                     bool ok;
                     const int64_t ad = addr(t, lo, c, ok);
-                    if (ok && c >= f0 && c < W) X[ad] = acc[t][mb][v];
+                    double v = 0.0;
+                    if (ok && c < W) v = X[ad];
+                    xb[t][kk] = v;
                 }
-        if (k == klast) break;
-        // carry local 0 .. q-2 to local r .. W-1 of window k-1, load its new
-        // indices 0 .. r-1
-        const int64_t lon = lo - R;
+        }
+        for (int64_t k = kfirst; k >= klast; --k) {
+            const int64_t lo = j1 + k * R;
+            const double *Fk = Fs + k * (KW * KW);
+            f64x4 acc[TRW][MB];
 #pragma unroll
-        for (int t = 0; t < TRW; ++t) {
+            for (int t = 0; t < TRW; ++t)
 #pragma unroll
-            for (int kk = 0; kk < RS; ++kk) {
-                const int c = 4 * kk + g;
-                xb[t][kk + RS] = (c < q - 1) ? acc[t][kk >> 2][kk & 3] : 0.0;
+                for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                double af[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) af[mb] = Fk[(mb * KK + kk) * 64 + lane];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int t = 0; t < TRW; ++t)
+                        acc[t][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], xb[t][kk], acc[t][mb], 0, 0, 0);
             }
+            // finished indices go back to HBM
+            const int64_t f0 = (k == klast) ? 0 : q - 1;
 #pragma unroll
-            for (int kk = 0; kk < RS; ++kk) {
-                const int c = 4 * kk + g;
-                bool ok;
-                const int64_t ad = addr(t, lon, c, ok);
-                double v = 0.0;
-                if (ok) v = X[ad];
-                xb[t][kk] = v;
+            for (int t = 0; t < TRW; ++t)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = 16 * mb + 4 * v + g;
+                        bool ok;
+                        const int64_t ad = addr(t, lo, c, ok);
+                        if (ok && c >= f0 && c < W) X[ad] = acc[t][mb][v];
+                    }
+            if (k == klast) break;
+            // carry local 0 .. q-2 to local r .. W-1 of window k-1, load its new
+            // indices 0 .. r-1
+            const int64_t lon = lo - R;
+#pragma unroll
+            for (int t = 0; t < TRW; ++t) {
+#pragma unroll
+                for (int kk = 0; kk < RS; ++kk) {
+                    const int c = 4 * kk + g;
+                    xb[t][kk + RS] = (c < q - 1) ? acc[t][kk >> 2][kk & 3] : 0.0;
+                }
+#pragma unroll
+                for (int kk = 0; kk < RS; ++kk) {
+                    const int c = 4 * kk + g;
+                    bool ok;
+                    const int64_t ad = addr(t, lon, c, ok);
+                    double v = 0.0;
+                    if (ok) v = X[ad];
+                    xb[t][kk] = v;
+                }
             }
+        }
+    }
+    if (epi) {
+        // the wavefront's last window is in memory; the epilogue's loads may
+        // read what other lanes stored
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        left_epilogue<double>(a, J, p0, 16 * TRW, lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) {
+#pragma unroll
+            for (int t = 0; t < TRW; ++t)            // flags of the tiles of 16 columns that exist
+                if (b * TRW + t < (n + 15) / 16)
+                    __hip_atomic_fetch_add(a.epi.flags + b * TRW + t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

@@ -9,11 +9,11 @@ not part of the reduction).
         HBM bytes per dispatch of each kernel: FETCH_SIZE and WRITE_SIZE (KiB per
         dispatch) scaled by what the same counters read for a plain device copy
         of COPY_BYTES bytes (the largest dispatch of the copy run)
-    python -m paper_2301_07964_amd.profiling record FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR COPY_BYTES
+    python -m paper_2301_07964_amd.profiling record FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR COPY_BYTES [NOTE]
         the same, as the record bench.py reads (profiles/pmc_traffic.json): the
         stage-two kernels of the real r = 32 path, each with the sha256 of the
         sources it is built from, so that bench.py uses a figure only while the
-        kernel is unchanged
+        kernel is unchanged; NOTE (optional) says how the counted run was made
     python -m paper_2301_07964_amd.profiling mfma DIR
         FP64 matrix-core use per kernel from a pass with SQ_INSTS_VALU_MFMA_MOPS_F64,
         SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (markdown table)
@@ -123,9 +123,11 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
-def record(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+def record(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, note=None):
     t = traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes)
     out = {"read_factor": t["read_factor"], "write_factor": t["write_factor"], "kernels": {}}
+    if note:
+        out["note"] = note
     for key, (kname, srcs) in RECORD_KERNELS.items():
         k = t["kernels"].get(kname)
         if not k:
@@ -180,7 +182,8 @@ def main(argv):
     elif len(argv) >= 6 and argv[0] == "traffic":
         print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], float(argv[5])), indent=1))
     elif len(argv) >= 6 and argv[0] == "record":
-        print(json.dumps(record(argv[1], argv[2], argv[3], argv[4], float(argv[5])), indent=1))
+        print(json.dumps(record(argv[1], argv[2], argv[3], argv[4], float(argv[5]),
+                                argv[6] if len(argv) > 6 else None), indent=1))
     elif len(argv) >= 2 and argv[0] == "mfma":
         print(mfma_table(argv[1]))
     else:

@@ -159,8 +159,9 @@ int ht_stream_status(void *stream);
  *     the left updates of group g are still in progress (Section 3.3's
  *     lookahead: each tile of 16 columns of the left pass announces when its
  *     part of the next group's band is final, and the generation waits for
- *     exactly the tiles it reads); real pencils with r in {4, 8, 16, 32} on
- *     the allocating entry points.  0 runs the groups one after the other.
+ *     exactly the tiles it reads); real and complex pencils with r in
+ *     {4, 8, 16, 32} on the allocating entry points.  0 runs the groups one
+ *     after the other.
  */
 #define HT_KNOB_WAIT_POLLS 1
 #define HT_KNOB_UPDATE_TILE_ROWS 2

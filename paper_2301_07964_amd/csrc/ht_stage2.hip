@@ -9,8 +9,8 @@
 //   3. application phase (ht_update.hpp): right updates of H, T, Z and Q,
 //      then left updates of H and T.
 // The Q and Z updates of a group run on an auxiliary stream, beside the next
-// group's work on the caller's stream.  With lookahead (real, r in {4, 8, 16,
-// 32}) the left pass of group g and then group g's Q and Z updates run on a
+// group's work on the caller's stream.  With lookahead (r in {4, 8, 16, 32})
+// the left pass of group g and then group g's Q and Z updates run on a
 // second stream, while group g+1's generation runs on the caller's stream,
 // reading each tile of its scratch band once the left pass has written it.
 // Every call joins its streams into the caller's stream before it returns.
@@ -227,10 +227,21 @@ static int launch_update(bool right, const UpdArgs<S> &ua, int64_t panels, hipSt
 
 // Matrix-core application kernels (real, r in {4, 8, 16, 32}).  Each job's
 // npanels counts wavefront tiles of 16*TRW rows (right) / columns (left).
+// coop: the H/T right pass of the lookahead schedule at r = 32, which has
+// the device to itself (the Q/Z update runs after the left pass): one tile of
+// 16 rows per workgroup, the window's product split over its four wavefronts
+// (n = 8192: 209 ms to 121 ms per reduction, the same arithmetic, bitwise;
+// n = 16384: 864 ms to 848 ms)
 template <int R>
-static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, hipStream_t st)
+static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, hipStream_t st, bool coop = false)
 {
     if constexpr (R == 32) {
+        if (!left && coop) {
+            int64_t tot = 0;
+            for (int i = 0; i < ua.njobs; ++i) { ua.job[i].npanels = (ua.n + 15) / 16; tot += ua.job[i].npanels; }
+            hipLaunchKernelGGL((k_update_mfma_coop<R, false, 1>), dim3((unsigned)tot), dim3(256), 0, st, ua, F);
+            return launch_check("k_update_mfma_coop(right)");
+        }
         if (left) {
             // left updates at r = 32: one tile of 16 columns per workgroup, the window's product split
             // over its four wavefronts (measured: n = 8192 87 ms against 224 ms for one LDS-staged tile
@@ -257,13 +268,13 @@ static int launch_update_mfma_r(bool left, UpdArgs<double> ua, const double *F, 
     return launch_check(left ? "k_update_mfma(left)" : "k_update_mfma(right)");
 }
 
-static int launch_update_mfma(bool left, const UpdArgs<double> &ua, const double *F, hipStream_t st)
+static int launch_update_mfma(bool left, const UpdArgs<double> &ua, const double *F, hipStream_t st, bool coop)
 {
     switch (ua.r) {
     case 4: return launch_update_mfma_r<4>(left, ua, F, st);
     case 8: return launch_update_mfma_r<8>(left, ua, F, st);
     case 16: return launch_update_mfma_r<16>(left, ua, F, st);
-    case 32: return launch_update_mfma_r<32>(left, ua, F, st);
+    case 32: return launch_update_mfma_r<32>(left, ua, F, st, coop);
     default: return HT_ERR_NOTSUP;
     }
 }
@@ -331,10 +342,10 @@ static int launch_form_factors(int64_t r, int64_t q, int64_t kmax, int64_t kext,
 // dispatch of one update pass: matrix cores for r in {4, 8, 16, 32}, the
 // vector kernels otherwise
 template <class S>
-static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S *F, hipStream_t st)
+static int launch_pass(bool right, const UpdArgs<S> &ua, int64_t panels, const S *F, hipStream_t st, bool coop = false)
 {
     if constexpr (sizeof(S) == 8) {
-        if (F) return launch_update_mfma(!right, ua, (const double *)F, st);
+        if (F) return launch_update_mfma(!right, ua, (const double *)F, st, coop);
     } else {
         if (F) return launch_update_mfma_z(!right, ua, (const double *)F, st);
     }
@@ -451,7 +462,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     // group's band copy in its per-tile epilogue), then group g's Q and Z
     // updates, on a second stream; the generation of group g+1 waits for the
     // tiles of the band it reads
-    const bool la = !fx && mf && sizeof(S) == 8 && knob(HT_KNOB_LOOKAHEAD) != 0;
+    const bool la = !fx && mf && knob(HT_KNOB_LOOKAHEAD) != 0;
     const bool aux = qz && !fx && !la;               // otherwise Q and Z on the auxiliary stream
     AuxCtx *ax = (aux || la) ? aux_ctx(st) : nullptr;
     if ((aux || la) && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
@@ -544,7 +555,7 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         addjob(T, 1, (q + 1) * rr, 1);
         ua.njobs = nj;
         { ProfScope ps(prof ? 2 : -1, st);
-        if ((rc = launch_pass<S>(true, ua, tot, F, st))) return rc; }
+        if ((rc = launch_pass<S>(true, ua, tot, F, st, la))) return rc; }
         nj = 0; tot = 0;
         addjob(H, 0, (q + 1) * rr, 0);
         addjob(T, 0, (q + 1) * rr, 1);

@@ -293,6 +293,10 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
     for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
     if (b >= J.npanels) return;
     const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax, kext = a.kext;
+    // left with lookahead epilogues: from the first tile the next group's
+    // generation reads rightwards, the tiles left of it last
+    const bool epi = LEFT && a.epi.flags != nullptr;
+    if (epi) b = (b + (a.epi.c0 < n ? a.epi.c0 / 16 : 0)) % J.npanels;
     const int64_t W = q + R - 1;
     const int g = lane >> 4, li = lane & 15;
     const int64_t p0 = b * 16;                      // first row (right) / column (left) of the tile
@@ -307,84 +311,96 @@ __global__ __launch_bounds__(256) void k_update_mfma_z(UpdArgs<zd> a, const doub
             if (klast >= kmax) return;
         } else {
             while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
-            if (kfirst < 0) return;
+            if (kfirst < 0 && !epi) return;
         }
     }
-    auto addr = [&](int64_t lo, int c, bool &ok) -> int64_t {
-        const int64_t fixed = p0 + li, idx = lo + c;
-        ok = fixed < n && idx < n;
-        return LEFT ? idx + fixed * ld : fixed + idx * ld;
-    };
+    if (kfirst >= klast) {                         // the tile takes part in at least one window
+        auto addr = [&](int64_t lo, int c, bool &ok) -> int64_t {
+            const int64_t fixed = p0 + li, idx = lo + c;
+            ok = fixed < n && idx < n;
+            return LEFT ? idx + fixed * ld : fixed + idx * ld;
+        };
 
-    double xr[KK], xi[KK];
-    {
-        const int64_t lo = j1 + kfirst * R;
+        double xr[KK], xi[KK];
+        {
+            const int64_t lo = j1 + kfirst * R;
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            const int c = 4 * kk + g;
-            bool ok;
-            const int64_t ad = addr(lo, c, ok);
-            zd v = zero<zd>();
-            if (ok && c < W) v = X[ad];
-            xr[kk] = v.re;
-            xi[kk] = v.im;
-        }
-    }
-    for (int64_t k = kfirst; k >= klast; --k) {
-        const int64_t lo = j1 + k * R;
-        const double *Fr = Fs + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
-        // the next window's new indices (lo-r .. lo-1) are not written by this
-        // window: load them now so that their latency overlaps the products
-        double nr[RS], ni[RS];
-#pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const int c = 4 * kk + g;
-            bool ok;
-            const int64_t ad = addr(lo - R, c, ok);
-            zd v = zero<zd>();
-            if (ok && k > klast) v = X[ad];
-            nr[kk] = v.re;
-            ni[kk] = v.im;
-        }
-        f64x4 ar[MB], ai[MB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) { ar[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; ai[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; }
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            double fr[MB], fi[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                fr[mb] = Fr[(mb * KK + kk) * 64 + lane];
-                fi[mb] = LEFT ? -Fi[(mb * KK + kk) * 64 + lane] : Fi[(mb * KK + kk) * 64 + lane];
-            }
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xr[kk], ar[mb], 0, 0, 0);
-                ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[mb], xi[kk], ar[mb], 0, 0, 0);
-                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xi[kk], ai[mb], 0, 0, 0);
-                ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[mb], xr[kk], ai[mb], 0, 0, 0);
-            }
-        }
-        const int64_t f0 = (k == klast) ? 0 : q - 1;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = 16 * mb + 4 * v + g;
+            for (int kk = 0; kk < KK; ++kk) {
+                const int c = 4 * kk + g;
                 bool ok;
                 const int64_t ad = addr(lo, c, ok);
-                if (ok && c >= f0 && c < W) X[ad] = mk<zd>(ar[mb][v], ai[mb][v]);
+                zd v = zero<zd>();
+                if (ok && c < W) v = X[ad];
+                xr[kk] = v.re;
+                xi[kk] = v.im;
             }
-        if (k == klast) break;
-#pragma unroll
-        for (int kk = 0; kk < RS; ++kk) {
-            const int c = 4 * kk + g;
-            const bool keep = c < q - 1;
-            xr[kk + RS] = keep ? ar[kk >> 2][kk & 3] : 0.0;
-            xi[kk + RS] = keep ? ai[kk >> 2][kk & 3] : 0.0;
         }
+        for (int64_t k = kfirst; k >= klast; --k) {
+            const int64_t lo = j1 + k * R;
+            const double *Fr = Fs + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
+            // the next window's new indices (lo-r .. lo-1) are not written by this
+            // window: load them now so that their latency overlaps the products
+            double nr[RS], ni[RS];
 #pragma unroll
-        for (int kk = 0; kk < RS; ++kk) { xr[kk] = nr[kk]; xi[kk] = ni[kk]; }
+            for (int kk = 0; kk < RS; ++kk) {
+                const int c = 4 * kk + g;
+                bool ok;
+                const int64_t ad = addr(lo - R, c, ok);
+                zd v = zero<zd>();
+                if (ok && k > klast) v = X[ad];
+                nr[kk] = v.re;
+                ni[kk] = v.im;
+            }
+            f64x4 ar[MB], ai[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) { ar[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; ai[mb] = f64x4{0.0, 0.0, 0.0, 0.0}; }
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                double fr[MB], fi[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    fr[mb] = Fr[(mb * KK + kk) * 64 + lane];
+                    fi[mb] = LEFT ? -Fi[(mb * KK + kk) * 64 + lane] : Fi[(mb * KK + kk) * 64 + lane];
+                }
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xr[kk], ar[mb], 0, 0, 0);
+                    ar[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[mb], xi[kk], ar[mb], 0, 0, 0);
+                    ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[mb], xi[kk], ai[mb], 0, 0, 0);
+                    ai[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[mb], xr[kk], ai[mb], 0, 0, 0);
+                }
+            }
+            const int64_t f0 = (k == klast) ? 0 : q - 1;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 16 * mb + 4 * v + g;
+                    bool ok;
+                    const int64_t ad = addr(lo, c, ok);
+                    if (ok && c >= f0 && c < W) X[ad] = mk<zd>(ar[mb][v], ai[mb][v]);
+                }
+            if (k == klast) break;
+#pragma unroll
+            for (int kk = 0; kk < RS; ++kk) {
+                const int c = 4 * kk + g;
+                const bool keep = c < q - 1;
+                xr[kk + RS] = keep ? ar[kk >> 2][kk & 3] : 0.0;
+                xi[kk + RS] = keep ? ai[kk >> 2][kk & 3] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < RS; ++kk) { xr[kk] = nr[kk]; xi[kk] = ni[kk]; }
+        }
+    }
+    if (epi) {
+        // the wavefront's last window is in memory; the epilogue's loads may
+        // read what other lanes stored
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        left_epilogue<zd>(a, J, p0, 16, lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_fetch_add(a.epi.flags + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -403,10 +419,10 @@ namespace ht {
 // dimension; the next window's new indices and factor fragments are loaded
 // before the current window's products.  Tiles with the longest sequences of
 // windows (top rows for right updates, rightmost columns for left updates)
-// are dispatched first, jobs interleaved.  The library launches the left form
-// with TC = 1; TC = 2, and the right form for H and T (faster by itself, but
-// then overlapping the Q, Z update on the other stream), were no faster over a
-// whole reduction.
+// are dispatched first, jobs interleaved.  The library launches both forms
+// with TC = 1: the left form always at r = 32, the right form for H and T in
+// the lookahead schedule (where no Q, Z update runs beside it; beside one, it
+// was no faster over a whole reduction).  TC = 2 was no faster.
 template <int R, bool LEFT, int TC>
 __global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, const double *F)
 {
@@ -566,9 +582,14 @@ __global__ __launch_bounds__(256) void k_update_mfma_z_coop_left(UpdArgs<zd> a, 
     UpdJob<zd> J = a.job[0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) if (jid == i) J = a.job[i];
-    const int64_t b = J.npanels - 1 - (int64_t)(blockIdx.x / a.njobs);   // rightmost tiles first
-    if (b < 0) return;
+    // rightmost tiles (most windows) first, unless the next group's
+    // generation waits for the tiles' epilogues: then from the first tile it
+    // reads rightwards, the tiles left of it last
+    const bool epi = a.epi.flags != nullptr;
+    const int64_t bi = (int64_t)(blockIdx.x / a.njobs);
+    if (bi >= J.npanels) return;
     const int64_t n = a.n, q = a.q, j1 = a.j1, kmax = a.kmax;
+    const int64_t b = !epi ? J.npanels - 1 - bi : (bi + (a.epi.c0 < n ? a.epi.c0 / 16 : 0)) % J.npanels;
     const int W = (int)(q + R - 1);
     const int g = lane >> 4, li = lane & 15;
     const int64_t p0 = b * 16;
@@ -576,86 +597,98 @@ __global__ __launch_bounds__(256) void k_update_mfma_z_coop_left(UpdArgs<zd> a, 
     const int64_t ld = J.ld;
 
     int64_t kfirst = kmax - 1;
+    const int64_t klast = 0;
     if (J.lim >= 0) {
         while (kfirst >= 0 && !(p0 + 16 > j1 + kfirst * R - J.lim)) --kfirst;
-        if (kfirst < 0) return;
+        if (kfirst < 0 && !epi) return;
     }
-    // whole window: row tid % 64 of columns tid / 64 + 4i; new rows: row
-    // tid % 32 of columns tid / 32 + 8i
-    const int wr = tid & 63, wc = tid >> 6, nr = tid & 31, nc = tid >> 5;
-    {
-        const int64_t lo = j1 + kfirst * R;
+    if (kfirst >= klast) {                         // the tile takes part in at least one window
+        // whole window: row tid % 64 of columns tid / 64 + 4i; new rows: row
+        // tid % 32 of columns tid / 32 + 8i
+        const int wr = tid & 63, wc = tid >> 6, nr = tid & 31, nc = tid >> 5;
+        {
+            const int64_t lo = j1 + kfirst * R;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = wc + 4 * i;
-            const int64_t col = p0 + j, row = lo + wr;
-            zd v = zero<zd>();
-            if (wr < W && col < n && row < n) v = X[row + col * ld];
-            buf[0][j * LT + wr] = v;
-            buf[1][j * LT + wr] = zero<zd>();      // indices >= W of the other buffer stay zero
+            for (int i = 0; i < 4; ++i) {
+                const int j = wc + 4 * i;
+                const int64_t col = p0 + j, row = lo + wr;
+                zd v = zero<zd>();
+                if (wr < W && col < n && row < n) v = X[row + col * ld];
+                buf[0][j * LT + wr] = v;
+                buf[1][j * LT + wr] = zero<zd>();      // indices >= W of the other buffer stay zero
+            }
         }
-    }
-    zd pre[2];
-    auto load_new = [&](int64_t kn) {
-        const int64_t lo = j1 + kn * R;
+        zd pre[2];
+        auto load_new = [&](int64_t kn) {
+            const int64_t lo = j1 + kn * R;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int64_t col = p0 + nc + 8 * i, row = lo + nr;
-            pre[i] = (col < n && row < n) ? X[row + col * ld] : zero<zd>();
-        }
-    };
-    if (kfirst > 0) load_new(kfirst - 1);
-    double fr[KK], fi[KK];
-    auto load_f = [&](int64_t k, double (&r_)[KK], double (&i_)[KK]) {
-        const double *Fr = F + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
+            for (int i = 0; i < 2; ++i) {
+                const int64_t col = p0 + nc + 8 * i, row = lo + nr;
+                pre[i] = (col < n && row < n) ? X[row + col * ld] : zero<zd>();
+            }
+        };
+        if (kfirst > 0) load_new(kfirst - 1);
+        double fr[KK], fi[KK];
+        auto load_f = [&](int64_t k, double (&r_)[KK], double (&i_)[KK]) {
+            const double *Fr = F + k * 2 * (KW * KW), *Fi = Fr + KW * KW;
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            r_[kk] = Fr[(wv * KK + kk) * 64 + lane];
-            i_[kk] = -Fi[(wv * KK + kk) * 64 + lane];          // U^H: conjugate
-        }
-    };
-    load_f(kfirst, fr, fi);
-    __syncthreads();
-    int cur = 0;
-    for (int64_t k = kfirst; k >= 0; --k) {
-        const int64_t lo = j1 + k * R;
-        double frn[KK], fin[KK];
-        if (k > 0) load_f(k - 1, frn, fin);
-        f64x4 ar = f64x4{0.0, 0.0, 0.0, 0.0}, ai = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            const zd v = buf[cur][li * LT + 4 * kk + g];
-            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.re, ar, 0, 0, 0);
-            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[kk], v.im, ar, 0, 0, 0);
-            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.im, ai, 0, 0, 0);
-            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[kk], v.re, ai, 0, 0, 0);
-        }
-        const int f0 = (k == 0) ? 0 : (int)(q - 1);
-        const int nxt = cur ^ 1;
-        __syncthreads();                            // the previous window's stores have read ob
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int c = 16 * wv + 4 * v + g;
-            const zd z = mk<zd>(ar[v], ai[v]);
-            if (c >= f0 && c < W) ob[li * LT + c] = z;
-            if (k > 0 && c < q - 1) buf[nxt][li * LT + c + R] = z;   // index c + R of window k-1
-        }
-        if (k > 0) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) buf[nxt][(nc + 8 * i) * LT + nr] = pre[i];
-        }
+            for (int kk = 0; kk < KK; ++kk) {
+                r_[kk] = Fr[(wv * KK + kk) * 64 + lane];
+                i_[kk] = -Fi[(wv * KK + kk) * 64 + lane];          // U^H: conjugate
+            }
+        };
+        load_f(kfirst, fr, fi);
         __syncthreads();
+        int cur = 0;
+        for (int64_t k = kfirst; k >= 0; --k) {
+            const int64_t lo = j1 + k * R;
+            double frn[KK], fin[KK];
+            if (k > 0) load_f(k - 1, frn, fin);
+            f64x4 ar = f64x4{0.0, 0.0, 0.0, 0.0}, ai = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = wc + 4 * i;
-            const int64_t col = p0 + j, row = lo + wr;
-            if (wr >= f0 && wr < W && col < n && row < n) X[row + col * ld] = ob[j * LT + wr];
+            for (int kk = 0; kk < KK; ++kk) {
+                const zd v = buf[cur][li * LT + 4 * kk + g];
+                ar = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.re, ar, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-fi[kk], v.im, ar, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fr[kk], v.im, ai, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f64_16x16x4f64(fi[kk], v.re, ai, 0, 0, 0);
+            }
+            const int f0 = (k == 0) ? 0 : (int)(q - 1);
+            const int nxt = cur ^ 1;
+            __syncthreads();                            // the previous window's stores have read ob
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * wv + 4 * v + g;
+                const zd z = mk<zd>(ar[v], ai[v]);
+                if (c >= f0 && c < W) ob[li * LT + c] = z;
+                if (k > 0 && c < q - 1) buf[nxt][li * LT + c + R] = z;   // index c + R of window k-1
+            }
+            if (k > 0) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) buf[nxt][(nc + 8 * i) * LT + nr] = pre[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = wc + 4 * i;
+                const int64_t col = p0 + j, row = lo + wr;
+                if (wr >= f0 && wr < W && col < n && row < n) X[row + col * ld] = ob[j * LT + wr];
+            }
+            if (k == 0) break;
+            if (k > 1) load_new(k - 2);
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) { fr[kk] = frn[kk]; fi[kk] = fin[kk]; }
+            cur = nxt;
         }
-        if (k == 0) break;
-        if (k > 1) load_new(k - 2);
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) { fr[kk] = frn[kk]; fi[kk] = fin[kk]; }
-        cur = nxt;
+    }
+    if (epi) {
+        __syncthreads();                           // the tile's last window is in memory
+        left_epilogue<zd>(a, J, p0, 16, tid, 256);
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(a.epi.flags + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 

@@ -362,29 +362,31 @@ def _with_lookahead(on, fn):
         ht.set_knob(ht.KNOB_LOOKAHEAD, old)
 
 
-@pytest.mark.parametrize("n,r,q,jmax,acc,trw", [
-    (900, 32, 32, -1, True, 0), (2100, 32, 32, -1, True, 0), (1500, 32, 7, -1, True, 0),
-    (1200, 32, 32, 70, True, 0), (1000, 32, 32, -1, False, 0), (33, 32, 32, -1, True, 0),
-    (4096, 32, 32, 96, True, 0), (1000, 16, 16, -1, True, 0), (1030, 16, 16, -1, True, 2),
-    (777, 8, 5, -1, True, 1), (1111, 8, 8, -1, True, 2), (500, 4, 4, -1, True, 0), (300, 4, 3, 100, False, 2)])
-def test_lookahead_is_bitwise_the_sequential_order(n, r, q, jmax, acc, trw):
-    """Lookahead (Section 3.3; real, r in {4, 8, 16, 32}): the generation of
-    group g+1 runs while the left updates of group g are in progress, reading
-    each tile of its scratch band once that tile's epilogue has written it.
-    Every kernel does the same arithmetic on the same values as in the
-    sequential order, so the outputs are bitwise equal; n not a multiple of
-    16 (and, with two 16-column tiles per wavefront, an odd number of
-    tiles), groups cut by jmax, q < r, no accumulation and a single group
-    are covered."""
+@pytest.mark.parametrize("n,r,q,jmax,acc,trw,cplx", [
+    (900, 32, 32, -1, True, 0, False), (2100, 32, 32, -1, True, 0, False), (1500, 32, 7, -1, True, 0, False),
+    (1200, 32, 32, 70, True, 0, False), (1000, 32, 32, -1, False, 0, False), (33, 32, 32, -1, True, 0, False),
+    (4096, 32, 32, 96, True, 0, False), (1000, 16, 16, -1, True, 0, False), (1030, 16, 16, -1, True, 2, False),
+    (777, 8, 5, -1, True, 1, False), (1111, 8, 8, -1, True, 2, False), (500, 4, 4, -1, True, 0, False),
+    (300, 4, 3, 100, False, 2, False), (700, 32, 32, -1, True, 0, True), (530, 16, 16, -1, True, 0, True),
+    (333, 8, 5, -1, True, 0, True), (400, 4, 4, 150, False, 0, True), (700, 32, 11, 90, True, 0, True)])
+def test_lookahead_is_bitwise_the_sequential_order(n, r, q, jmax, acc, trw, cplx):
+    """Lookahead (Section 3.3; r in {4, 8, 16, 32}): the generation of group
+    g+1 runs while the left updates of group g are in progress, reading each
+    tile of its scratch band once that tile's epilogue has written it.  Every
+    kernel does the same arithmetic on the same values as in the sequential
+    order, so the outputs are bitwise equal; real and complex pencils, n not
+    a multiple of 16 (and, with two 16-column tiles per wavefront, an odd
+    number of tiles), groups cut by jmax, q < r, no accumulation and a
+    single group are covered."""
     ht = _ht()
-    H, T = inputs.rht_pencil(n, r, 17)
-    print(f"[lookahead] n={n} r={r} q={q} jmax={jmax} acc={acc} tile rows={trw}", flush=True)
+    H, T = (inputs.rht_pencil_complex if cplx else inputs.rht_pencil)(n, r, 17)
+    print(f"[lookahead] n={n} r={r} q={q} jmax={jmax} acc={acc} tile rows={trw} complex={cplx}", flush=True)
     old_trw = ht.set_knob(ht.KNOB_UPDATE_TILE_ROWS, trw)
 
     def run():
         Hd, Td = ht.colmajor(H), ht.colmajor(T)
-        Qd = ht.colmajor(np.eye(n)) if acc else None
-        Zd = ht.colmajor(np.eye(n)) if acc else None
+        Qd = ht.colmajor(np.eye(n, dtype=H.dtype)) if acc else None
+        Zd = ht.colmajor(np.eye(n, dtype=H.dtype)) if acc else None
         ht.stage2(Hd, Td, min(r, n - 1), Qd, Zd, q=min(q, n - 1), jmax=jmax)
         torch.cuda.synchronize()
         assert ht.stream_status() == 0

@@ -28,6 +28,19 @@
 
 namespace ht {
 
+// Store of a finished entry of the real update kernels: a relaxed store at
+// system scope, which writes through the L2 instead of leaving the line dirty
+// there.  The generation kernel runs beside these kernels (lookahead) and
+// writes back its XCD's whole L2 at every step's release; with fewer dirty
+// lines from the updates, those write-backs are shorter (n = 16384, r = 32:
+// 5.37 s to 5.27 s per reduction; nontemporal stores: 5.32 s).  No ordering
+// is implied: the kernels' results are ordered by stream order and the
+// lookahead flags as before.
+__device__ __forceinline__ void st_out(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // order of the embedded window factor for block size R
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(256) void k_update_mfma(UpdArgs<double> a, const do
                         const int c = 16 * mb + 4 * v + g;
                         bool ok;
                         const int64_t ad = addr(t, lo, c, ok);
-                        if (ok && c >= f0 && c < W) X[ad] = acc[t][mb][v];
+                        if (ok && c >= f0 && c < W) st_out(X + ad, acc[t][mb][v]);
                     }
             if (k == klast) break;
             // carry local 0 .. q-2 to local r .. W-1 of window k-1, load its new
@@ -544,7 +557,7 @@ __global__ __launch_bounds__(256) void k_update_mfma_coop(UpdArgs<double> a, con
                 wmap(tid + 256 * i, j, c);
                 bool ok;
                 const int64_t ad = at(j, lo, c, ok);
-                if (ok && c >= f0 && c < W) X[ad] = ow[j * LT + c];
+                if (ok && c >= f0 && c < W) st_out(X + ad, ow[j * LT + c]);
             }
             if (!more) break;
             if (k - 1 > klast) load_new(k - 2);

@@ -309,8 +309,13 @@ __device__ __forceinline__ void gen_far(const GenArgs<S> &a, int w, int part)
     if (tid == 0) st_release(mine, kAllDone);
 }
 
-// Stage the left reflectors V (v_s at lv[s*r ..]) and the columns of their WY
-// factor T (column s at lT[s*kMaxR ..]) of block kk of the earlier sweeps
+// Row stride of the staged reflectors and WY columns in LDS: a lane that
+// walks its own row (lazy_wy, wy_column) would otherwise hit the same bank as
+// every other lane (a stride of 32 doubles is 64 banks).
+constexpr int kLS = kMaxR + 1;
+
+// Stage the left reflectors V (v_s at lv[s*kLS ..]) and the columns of their
+// WY factor T (column s at lT[s*kLS ..]) of block kk of the earlier sweeps
 // s < nw into LDS, by NG groups of 32 threads (thread t: group t / 32, entry
 // t % 32; r <= 32): all loads are issued before any is stored, so they are in
 // flight together.
@@ -335,8 +340,8 @@ __device__ __forceinline__ void stage_lazy(const GenArgs<S> &a, int kk, int nw, 
     for (int it = 0; it < NS; ++it) {
         const int sw = g + NG * it;
         if (sw < nw) {
-            if (c < r) lv[sw * r + c] = tv[it];
-            lT[sw * kMaxR + c] = tt[it];
+            if (c < r) lv[sw * kLS + c] = tv[it];
+            lT[sw * kLS + c] = tt[it];
         }
     }
 }
@@ -356,24 +361,24 @@ __device__ __forceinline__ S lazy_wy(S x, int lane, int nw, int r, const S *lv, 
     S z0 = zero<S>(), z1 = zero<S>();              // z_i = v_i^H x   (lane i < nw)
     if (lane < nw)
         for (int t = 0; t < r; t += 2) {
-            z0 = add(z0, cmul(lv[lane * r + t], xs[lane + t]));
-            if (t + 1 < r) z1 = add(z1, cmul(lv[lane * r + t + 1], xs[lane + t + 1]));
+            z0 = add(z0, cmul(lv[lane * kLS + t], xs[lane + t]));
+            if (t + 1 < r) z1 = add(z1, cmul(lv[lane * kLS + t + 1], xs[lane + t + 1]));
         }
     if (lane < 32) zs[lane] = add(z0, z1);
     __builtin_amdgcn_wave_barrier();
     S u0 = zero<S>(), u1 = zero<S>();              // u = T^H z
     if (lane < nw)
         for (int jj = 0; jj <= lane; jj += 2) {
-            u0 = add(u0, cmul(lT[lane * kMaxR + jj], zs[jj]));
-            if (jj + 1 <= lane) u1 = add(u1, cmul(lT[lane * kMaxR + jj + 1], zs[jj + 1]));
+            u0 = add(u0, cmul(lT[lane * kLS + jj], zs[jj]));
+            if (jj + 1 <= lane) u1 = add(u1, cmul(lT[lane * kLS + jj + 1], zs[jj + 1]));
         }
     if (lane < 32) us[lane] = add(u0, u1);
     __builtin_amdgcn_wave_barrier();
     S a0 = zero<S>(), a1 = zero<S>();              // V u
     const int ilo = max(0, lane - r + 1), ihi = min(nw - 1, lane);
     for (int i = ilo; i <= ihi; i += 2) {
-        a0 = add(a0, mul(lv[i * r + (lane - i)], us[i]));
-        if (i + 1 <= ihi) a1 = add(a1, mul(lv[(i + 1) * r + (lane - i - 1)], us[i + 1]));
+        a0 = add(a0, mul(lv[i * kLS + (lane - i)], us[i]));
+        if (i + 1 <= ihi) a1 = add(a1, mul(lv[(i + 1) * kLS + (lane - i - 1)], us[i + 1]));
     }
     return sub(x, add(a0, a1));
 }
@@ -391,8 +396,8 @@ __device__ __forceinline__ void wy_column(int lane, int nw, int r, int m, const 
     if (lane < nw) {
         const int tlo = nw - lane, thi = min(r - 1, nw - lane + m - 1);
         for (int t = tlo; t <= thi; t += 2) {
-            z0 = add(z0, cmul(lv[lane * r + t], sv[lane + t - nw]));
-            if (t + 1 <= thi) z1 = add(z1, cmul(lv[lane * r + t + 1], sv[lane + t + 1 - nw]));
+            z0 = add(z0, cmul(lv[lane * kLS + t], sv[lane + t - nw]));
+            if (t + 1 <= thi) z1 = add(z1, cmul(lv[lane * kLS + t + 1], sv[lane + t + 1 - nw]));
         }
     }
     if (lane < 32) zs[lane] = add(z0, z1);
@@ -400,8 +405,8 @@ __device__ __forceinline__ void wy_column(int lane, int nw, int r, int m, const 
     if (lane < nw) {
         S c0 = zero<S>(), c1 = zero<S>();
         for (int jj = lane; jj < nw; jj += 2) {
-            c0 = add(c0, mul(lT[jj * kMaxR + lane], zs[jj]));
-            if (jj + 1 < nw) c1 = add(c1, mul(lT[(jj + 1) * kMaxR + lane], zs[jj + 1]));
+            c0 = add(c0, mul(lT[jj * kLS + lane], zs[jj]));
+            if (jj + 1 < nw) c1 = add(c1, mul(lT[(jj + 1) * kLS + lane], zs[jj + 1]));
         }
         out[lane] = sub(zero<S>(), mul(tau, add(c0, c1)));
     }
@@ -433,10 +438,12 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
     __shared__ S sv[64], sw[64];
     __shared__ S blk[32 * LB];
     __shared__ S stau[4];
-    __shared__ S lzv[2][kMaxR * kMaxR];          // staged lazy reflectors, by block parity
-    __shared__ S lzT[2][kMaxR * kMaxR];          // their WY factor T
+    __shared__ S lzv[2][kMaxR * kLS];            // staged lazy reflectors, by block parity
+    __shared__ S lzT[2][kMaxR * kLS];            // their WY factor T
     __shared__ S lws[2][128];                    // per-wavefront scratch of the WY products
-    __shared__ S nrw[64 * RM];                   // the near rows of the current step
+    constexpr int NRS = RM + 1;                  // row stride of nrw (a multiple of 32 doubles would put
+                                                 // every fourth lane on one bank)
+    __shared__ S nrw[64 * NRS];                  // the near rows of the current step
     __shared__ int s_go;
     int tready = (j1 - 1) >> 4;                  // lookahead: tiles of the band below this one are ready
 
@@ -542,7 +549,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
             if (full && e < m * mcols) blk[tbc[it] * LB + tbi[it]] = tb[it];
         }
 #pragma unroll
-        for (int c = 0; c < CP; ++c) nrw[(tid >> 2) * RM + part * CP + c] = xn[c];
+        for (int c = 0; c < CP; ++c) nrw[(tid >> 2) * NRS + part * CP + c] = xn[c];
         __syncthreads();
 
         // ---- B. lazy left updates (wave 0: H column jb, wave 1: T column
@@ -652,7 +659,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
 #pragma unroll
                 for (int c = 0; c < CP; ++c) {
                     const int cc = part * CP + c;
-                    xn[c] = nrw[(tid >> 2) * RM + cc];
+                    xn[c] = nrw[(tid >> 2) * NRS + cc];
                     ds = add(ds, mul(xn[c], sw[cc]));
                 }
                 ds = add(ds, shfl_(ds, lane ^ 1));         // every lane takes part in the exchange

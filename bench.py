@@ -434,9 +434,10 @@ def measured_traffic(kernel: str, lookahead: int = 0):
     (profiles/pmc_traffic.json), if it was taken on the current source of the
     kernel; None otherwise.  The counters are taken with the groups in
     sequence (counter collection runs one kernel at a time); with lookahead
-    the left pass also does the band copy and the exact zeros, so its figure
-    does not apply and None is returned for it."""
-    if lookahead and kernel == "k_update_mfma<left>":
+    the left pass also does the band copy and the exact zeros, and the H/T
+    right pass runs in another kernel (the four-wavefront tiles), so the
+    update kernels' figures do not apply and None is returned for them."""
+    if lookahead and kernel != "k_generate<double>":
         return None
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")

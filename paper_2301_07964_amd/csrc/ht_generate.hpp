@@ -349,38 +349,46 @@ __device__ __forceinline__ void stage_lazy(const GenArgs<S> &a, int kk, int nw, 
 // Q^H x for Q = G_0 ... G_{nw-1} = I - V T V^H, the compact WY form of the
 // left reflectors of one block of the earlier sweeps (G_i = I - tau_i v_i
 // v_i^H, v_i on rows base+i .. base+i+r-1): x <- x - V (T^H (V^H x)), equal
-// to applying G_0^H, G_1^H, ... in turn.  One wavefront; lane l holds the
-// entry of row base+l.  lv, lT as staged by stage_lazy; ws: 128 values of LDS
-// scratch of this wavefront.
+// to applying G_0^H, G_1^H, ... in turn.  Two wavefronts share one column
+// (half = 0 holds x, lane l the entry of row base+l; half = 1 helps): each
+// forms half of every sum of the three products (the terms t < (r+1)/2 or
+// the rest of V^H x, the terms of one parity of T^H z and of V u), so the
+// dependent chains are half as long.  Called by all four wavefronts of the
+// workgroup (the H column on wavefronts 0 and 2, the T column on 1 and 3)
+// with the workgroup's barriers between the products; act: this column
+// takes part.  lv, lT as staged by stage_lazy; ws: this column's LDS scratch
+// of 384 values.  Returns the result in the lanes of half 0.
 template <class S>
-__device__ __forceinline__ S lazy_wy(S x, int lane, int nw, int r, const S *lv, const S *lT, S *ws)
+__device__ __forceinline__ S lazy_wy(S x, int lane, int half, bool act, int nw, int r, const S *lv, const S *lT,
+                                     S *ws)
 {
-    S *xs = ws, *zs = ws + 64, *us = ws + 96;
-    xs[lane] = x;
-    __builtin_amdgcn_wave_barrier();
-    S z0 = zero<S>(), z1 = zero<S>();              // z_i = v_i^H x   (lane i < nw)
-    if (lane < nw)
-        for (int t = 0; t < r; t += 2) {
+    S *xs = ws, *zp = ws + 64, *up = ws + 128, *ap = ws + 192;   // zp, up: [2][32]; ap: [2][64]
+    if (half == 0) xs[lane] = x;
+    __syncthreads();
+    S z0 = zero<S>(), z1 = zero<S>();              // z_i = v_i^H x   (lane i < nw), half of the terms
+    if (act && lane < nw) {
+        const int hr = (r + 1) >> 1, t0 = half ? hr : 0, t1 = half ? r : hr;
+        for (int t = t0; t < t1; t += 2) {
             z0 = add(z0, cmul(lv[lane * kLS + t], xs[lane + t]));
-            if (t + 1 < r) z1 = add(z1, cmul(lv[lane * kLS + t + 1], xs[lane + t + 1]));
+            if (t + 1 < t1) z1 = add(z1, cmul(lv[lane * kLS + t + 1], xs[lane + t + 1]));
         }
-    if (lane < 32) zs[lane] = add(z0, z1);
-    __builtin_amdgcn_wave_barrier();
-    S u0 = zero<S>(), u1 = zero<S>();              // u = T^H z
-    if (lane < nw)
-        for (int jj = 0; jj <= lane; jj += 2) {
-            u0 = add(u0, cmul(lT[lane * kLS + jj], zs[jj]));
-            if (jj + 1 <= lane) u1 = add(u1, cmul(lT[lane * kLS + jj + 1], zs[jj + 1]));
-        }
-    if (lane < 32) us[lane] = add(u0, u1);
-    __builtin_amdgcn_wave_barrier();
-    S a0 = zero<S>(), a1 = zero<S>();              // V u
-    const int ilo = max(0, lane - r + 1), ihi = min(nw - 1, lane);
-    for (int i = ilo; i <= ihi; i += 2) {
-        a0 = add(a0, mul(lv[i * kLS + (lane - i)], us[i]));
-        if (i + 1 <= ihi) a1 = add(a1, mul(lv[(i + 1) * kLS + (lane - i - 1)], us[i + 1]));
     }
-    return sub(x, add(a0, a1));
+    if (lane < 32) zp[half * 32 + lane] = add(z0, z1);
+    __syncthreads();
+    S u0 = zero<S>();                              // u = T^H z, the terms jj of parity `half`
+    if (act && lane < nw)
+        for (int jj = half; jj <= lane; jj += 2) u0 = add(u0, cmul(lT[lane * kLS + jj], add(zp[jj], zp[32 + jj])));
+    if (lane < 32) up[half * 32 + lane] = u0;
+    __syncthreads();
+    S a0 = zero<S>();                              // V u, the terms i of parity `half`
+    if (act) {
+        const int ilo = max(0, lane - r + 1), ihi = min(nw - 1, lane);
+        for (int i = ilo + ((ilo ^ half) & 1); i <= ihi; i += 2)
+            a0 = add(a0, mul(lv[i * kLS + (lane - i)], add(up[i], up[32 + i])));
+    }
+    ap[half * 64 + lane] = a0;
+    __syncthreads();
+    return sub(x, add(ap[lane], ap[64 + lane]));
 }
 
 // Column nw of the WY factor T for the reflectors of block k of sweeps
@@ -440,7 +448,7 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
     __shared__ S stau[4];
     __shared__ S lzv[2][kMaxR * kLS];            // staged lazy reflectors, by block parity
     __shared__ S lzT[2][kMaxR * kLS];            // their WY factor T
-    __shared__ S lws[2][128];                    // per-wavefront scratch of the WY products
+    __shared__ S lws[2][384];                    // per-column scratch of the WY products
     constexpr int NRS = RM + 1;                  // row stride of nrw (a multiple of 32 doubles would put
                                                  // every fourth lane on one bank)
     __shared__ S nrw[64 * NRS];                  // the near rows of the current step
@@ -552,16 +560,20 @@ __global__ __launch_bounds__(256) void k_generate(GenArgs<S> a)
         for (int c = 0; c < CP; ++c) nrw[(tid >> 2) * NRS + part * CP + c] = xn[c];
         __syncthreads();
 
-        // ---- B. lazy left updates (wave 0: H column jb, wave 1: T column
-        // i1+r-1) with the left reflectors of block k of the earlier sweeps;
-        // then the left reflector from H(i1:i2, jb) (wave 0)
+        // ---- B. lazy left updates (H column jb on waves 0 and 2, T column
+        // i1+r-1 on waves 1 and 3) with the left reflectors of block k of the
+        // earlier sweeps; then the left reflector from H(i1:i2, jb) (wave 0)
+        S x = wid == 0 ? xh : xt;
+        if (nw > 0) {
+            // rows past the last lazy row (rowmax) take no part: the
+            // reflectors are zero there
+            const S y = lazy_wy<S>(x, lane, wid >> 1, (wid & 1) ? lazyT : lazyH, nw, r, lzv[buf], lzT[buf],
+                                   lws[wid & 1]);
+            if (wid < 2 && ((wid & 1) ? lazyT : lazyH)) x = y;
+        }
         if (wid < 2) {
             const bool isH = (wid == 0);
-            S x = isH ? xh : xt;
             if (isH ? lazyH : lazyT) {
-                // rows past the last lazy row (rowmax) take no part: the
-                // reflectors are zero there
-                x = lazy_wy<S>(x, lane, nw, r, lzv[buf], lzT[buf], lws[wid]);
                 // rows above the block go back now; the block's rows are
                 // reduced (H) or take part in the T block (T)
                 const int wlast = full ? i1 - 1 : rowmax;

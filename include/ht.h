@@ -160,8 +160,9 @@ int ht_stream_status(void *stream);
  *     lookahead: each tile of 16 columns of the left pass announces when its
  *     part of the next group's band is final, and the generation waits for
  *     exactly the tiles it reads); real and complex pencils with r in
- *     {4, 8, 16, 32} on the allocating entry points.  0 runs the groups one
- *     after the other.
+ *     {4, 8, 16, 32} on the allocating entry points, while no lookahead call
+ *     on another stream of the device is still running (otherwise that call
+ *     runs its groups in sequence).  0 runs the groups one after the other.
  */
 #define HT_KNOB_WAIT_POLLS 1
 #define HT_KNOB_UPDATE_TILE_ROWS 2

@@ -167,6 +167,11 @@ struct AuxCtx {
     hipStream_t left = nullptr;
     hipEvent_t rdone = nullptr, ldone = nullptr;
     int64_t delay_ticks = 0;      // kLaDelayUs in ticks of the device's constant-rate clock
+    // lookahead calls in flight: one being enqueued (pending), or the end of
+    // the last one enqueued on this stream (la_end, once recorded)
+    hipEvent_t la_end = nullptr;
+    bool la_pending = false, la_recorded = false;
+    int dev = 0;
     bool ok = false;
 };
 static std::mutex g_aux_mu;
@@ -188,11 +193,47 @@ static AuxCtx *aux_ctx(hipStream_t st)
     if (hipStreamCreateWithFlags(&c.left, hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (hipEventCreateWithFlags(&c.rdone, hipEventDisableTiming) != hipSuccess) return nullptr;
     if (hipEventCreateWithFlags(&c.ldone, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&c.la_end, hipEventDisableTiming) != hipSuccess) return nullptr;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
     c.delay_ticks = (int64_t)khz * kLaDelayUs / 1000;
+    c.dev = dev;
     c.ok = true;
     return &c;
+}
+
+// Lookahead makes the first sweep of a generation wait for the left pass of
+// the same call, which runs on another stream; a generation workgroup takes a
+// whole compute unit, so the generations of several calls running at once
+// on one device could hold every unit while their left passes wait for one.
+// A call therefore takes the lookahead schedule only while no other stream's
+// lookahead call is in flight on the device (being enqueued, or its end
+// event not yet reached); otherwise it runs its groups in sequence.  The
+// claim ends when the call has enqueued its work (LaClaim's destructor).
+struct LaClaim {
+    AuxCtx *c = nullptr;
+    ~LaClaim()
+    {
+        if (!c) return;
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        c->la_pending = false;
+    }
+};
+
+static bool claim_lookahead(AuxCtx *self, LaClaim &cl)
+{
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    bool busy = false;
+    for (auto &kv : g_aux) {
+        AuxCtx &o = kv.second;
+        if (busy || &o == self || !o.ok || o.dev != self->dev) continue;
+        busy = o.la_pending || (o.la_recorded && hipEventQuery(o.la_end) == hipErrorNotReady);
+    }
+    (void)hipGetLastError();                          // a query that returned not-ready leaves no error behind
+    if (busy) return false;
+    self->la_pending = true;
+    cl.c = self;
+    return true;
 }
 
 // Launch the application-phase kernels: register-ring variants for r in
@@ -462,10 +503,13 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     // group's band copy in its per-tile epilogue), then group g's Q and Z
     // updates, on a second stream; the generation of group g+1 waits for the
     // tiles of the band it reads
-    const bool la = !fx && mf && knob(HT_KNOB_LOOKAHEAD) != 0;
+    const bool want_la = !fx && mf && knob(HT_KNOB_LOOKAHEAD) != 0;
+    const bool need_ctx = (qz && !fx) || want_la;
+    AuxCtx *ax = need_ctx ? aux_ctx(st) : nullptr;
+    if (need_ctx && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
+    LaClaim claim;
+    const bool la = want_la && claim_lookahead(ax, claim);
     const bool aux = qz && !fx && !la;               // otherwise Q and Z on the auxiliary stream
-    AuxCtx *ax = (aux || la) ? aux_ctx(st) : nullptr;
-    if ((aux || la) && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
     const bool prof = !fx;                           // kernel timing creates events: not for fixed scratch
     const int64_t np = (n + 63) / 64;
     int *flags = la ? (int *)(ws + g.off_flags) : nullptr;
@@ -591,9 +635,12 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
         hipLaunchKernelGGL(k_clean<S>, dim3((unsigned)(n - cc0)), dim3(256), 0, st, H, T, ld, n, rr, j2, cc0, depth);
         if ((rc = launch_check("k_clean"))) return rc; }
     }
-    if (la) {    // join the left stream
+    if (la) {    // join the left stream; the call's end is what other streams' calls check
         if (hipEventRecord(ax->ldone, ax->left) != hipSuccess) return HT_ERR_HIP;
         if (hipStreamWaitEvent(st, ax->ldone, 0) != hipSuccess) return HT_ERR_HIP;
+        if (hipEventRecord(ax->la_end, st) != hipSuccess) return HT_ERR_HIP;
+        std::lock_guard<std::mutex> lk(g_aux_mu);
+        ax->la_recorded = true;
     }
     if (aux) {   // join the auxiliary stream
         if (hipEventRecord(ax->join, ax->aux) != hipSuccess) return HT_ERR_HIP;

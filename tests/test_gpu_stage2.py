@@ -401,6 +401,53 @@ def test_lookahead_is_bitwise_the_sequential_order(n, r, q, jmax, acc, trw, cplx
         assert np.array_equal(a, b)
 
 
+def test_concurrent_calls_on_several_streams():
+    """Four r = 32 reductions enqueued at once on four streams (the serving
+    loop's pattern).  A lookahead call's first sweep waits for the same call's
+    left pass, and each call's generation takes 3q = 96 whole compute units,
+    so only one stream's call at a time may take the lookahead schedule; the
+    others run their groups in sequence.  Every result must be bitwise that of
+    the sequential order on one stream, and no wait may give up."""
+    ht = _ht()
+    n, r = 1500, 32
+    pencils = [inputs.rht_pencil(n, r, 40 + i) for i in range(4)]
+    old = ht.set_knob(ht.KNOB_LOOKAHEAD, 0)
+    try:
+        ref = []
+        for H, T in pencils:
+            Hd, Td = ht.colmajor(H), ht.colmajor(T)
+            Qd, Zd = ht.colmajor(np.eye(n)), ht.colmajor(np.eye(n))
+            ht.stage2(Hd, Td, r, Qd, Zd)
+            torch.cuda.synchronize()
+            ref.append([ht.to_numpy(x) for x in (Hd, Td, Qd, Zd)])
+    finally:
+        ht.set_knob(ht.KNOB_LOOKAHEAD, old)
+    assert ht.stream_status() == 0
+    streams = [torch.cuda.Stream() for _ in pencils]
+    outs = []
+    for (H, T), st in zip(pencils, streams):
+        with torch.cuda.stream(st):
+            Hd, Td = ht.colmajor(H), ht.colmajor(T)
+            Qd, Zd = ht.colmajor(np.eye(n)), ht.colmajor(np.eye(n))
+        st.synchronize()
+        outs.append((Hd, Td, Qd, Zd))
+    print("[concurrent] enqueueing 4 calls", flush=True)
+    # a shorter wait limit (about a quarter of a second of polling): a wait
+    # that could not end would show as a timeout in the status, not as a stall
+    old_polls = ht.set_knob(ht.KNOB_WAIT_POLLS, 1 << 19)
+    try:
+        for (Hd, Td, Qd, Zd), st in zip(outs, streams):
+            ht.stage2(Hd, Td, r, Qd, Zd, stream=st)
+        torch.cuda.synchronize()
+    finally:
+        ht.set_knob(ht.KNOB_WAIT_POLLS, old_polls)
+    for st in streams:
+        assert ht.stream_status(st) == 0
+    for got, exp in zip(outs, ref):
+        for a, b in zip(got, exp):
+            assert np.array_equal(ht.to_numpy(a), b)
+
+
 def test_lookahead_parity_vs_oracle():
     """The lookahead path (the default at r = 32) against the oracle, with a
     group count that leaves a short last group."""

@@ -475,10 +475,11 @@ def main():
     ap.add_argument("--complex", action="store_true", help="stage1: complex128 pencil")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--count", type=int, default=2048, help="batched: number of pencils")
-    ap.add_argument("--lookahead", type=int, choices=(0, 1), default=1,
-                    help="single: 1 overlaps each group's generation with the previous group's left pass (the "
-                         "default), 0 runs the groups one after the other (for profilers that run one kernel at a "
-                         "time, where the overlapped schedule would wait on a kernel that cannot start)")
+    ap.add_argument("--lookahead", type=int, choices=(0, 1, 2), default=1,
+                    help="single: 1 (the default) overlaps each group's generation with the previous group's left "
+                         "pass from n = 1024 on, 2 at every n, 0 runs the groups one after the other (for "
+                         "profilers that run one kernel at a time, where the overlapped schedule would wait on a "
+                         "kernel that cannot start)")
     ap.add_argument("--wait-polls", type=int, default=0,
                     help="single: polls before a device-side wait gives up (0: the library default)")
     args = ap.parse_args()

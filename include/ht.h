@@ -155,14 +155,14 @@ int ht_stream_status(void *stream);
  *     makes every wait give up at once (used to test the failure path).
  *   HT_KNOB_UPDATE_TILE_ROWS [0]: tiles of 16 rows per wavefront in the
  *     matrix-core right updates; 0 = automatic (2 for n >= 8192), 1 or 2.
- *   HT_KNOB_LOOKAHEAD [1]: 1 lets the generate phase of group g+1 run while
+ *   HT_KNOB_LOOKAHEAD [1]: lets the generate phase of group g+1 run while
  *     the left updates of group g are still in progress (Section 3.3's
  *     lookahead: each tile of 16 columns of the left pass announces when its
  *     part of the next group's band is final, and the generation waits for
- *     exactly the tiles it reads); real and complex pencils with r in
- *     {4, 8, 16, 32} on the allocating entry points, while no lookahead call
- *     on another stream of the device is still running (otherwise that call
- *     runs its groups in sequence).  0 runs the groups one after the other.
+ *     exactly the tiles it reads): 0 never, 1 for n >= 1024, 2 always; real
+ *     and complex pencils with r in {4, 8, 16, 32} on the allocating entry
+ *     points, while no lookahead call on another stream of the device is
+ *     still running (otherwise that call runs its groups in sequence).
  */
 #define HT_KNOB_WAIT_POLLS 1
 #define HT_KNOB_UPDATE_TILE_ROWS 2

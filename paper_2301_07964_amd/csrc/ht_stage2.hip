@@ -144,6 +144,7 @@ inline int64_t default_q(int64_t n, int64_t r) { (void)n; return r; }
 // n = 16384, r = 32: 5.30 s a reduction with a pause of 10 us to 80 us,
 // 5.61 s without).  Bounded by the device's constant-rate clock.
 constexpr int kLaDelayUs = 10;
+constexpr int64_t kLaMinN = 1024;              // automatic lookahead from this order on
 __global__ void k_delay(int64_t ticks)
 {
     if (threadIdx.x == 0) {
@@ -503,7 +504,11 @@ static int stage2_impl(S *H, S *T, S *Q, S *Z, int64_t n, int64_t r, int64_t ld,
     // group's band copy in its per-tile epilogue), then group g's Q and Z
     // updates, on a second stream; the generation of group g+1 waits for the
     // tiles of the band it reads
-    const bool want_la = !fx && mf && knob(HT_KNOB_LOOKAHEAD) != 0;
+    // knob 1 (automatic): from n = 1024 on; for small pencils the pause and the
+    // stream hand-offs of every group cost more than the overlap saves (a loop
+    // of 2048 single calls with n up to 512: 30.2 s without, 32.6 s with)
+    const int64_t la_knob = knob(HT_KNOB_LOOKAHEAD);
+    const bool want_la = !fx && mf && (la_knob == 2 || (la_knob == 1 && n >= kLaMinN));
     const bool need_ctx = (qz && !fx) || want_la;
     AuxCtx *ax = need_ctx ? aux_ctx(st) : nullptr;
     if (need_ctx && !ax) { snprintf(g_errmsg, sizeof(g_errmsg), "auxiliary stream creation failed"); return HT_ERR_HIP; }
@@ -808,7 +813,7 @@ int ht_set_knob(int knob, int64_t value)
     switch (knob) {
     case HT_KNOB_WAIT_POLLS: if (value < 0) return -2; break;
     case HT_KNOB_UPDATE_TILE_ROWS: if (value < 0 || value > 2) return -2; break;
-    case HT_KNOB_LOOKAHEAD: if (value < 0 || value > 1) return -2; break;
+    case HT_KNOB_LOOKAHEAD: if (value < 0 || value > 2) return -2; break;
     default: break;
     }
     ht::knobs()[knob - 1].store(value, std::memory_order_relaxed);

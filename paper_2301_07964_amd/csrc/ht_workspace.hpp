@@ -22,7 +22,7 @@ inline std::atomic<int64_t> *knobs()
     static std::atomic<int64_t> k[kNumKnobs] = {
         {int64_t(1) << 22},   // HT_KNOB_WAIT_POLLS: polls before a device-side wait gives up
         {0},                  // HT_KNOB_UPDATE_TILE_ROWS: 0 automatic, 1 or 2 tiles of 16 rows per wavefront
-        {1},                  // HT_KNOB_LOOKAHEAD: generation of group g+1 overlaps the left updates of group g
+        {1},                  // HT_KNOB_LOOKAHEAD: 0 never, 1 from n = 1024 on, 2 always
     };
     return k;
 }

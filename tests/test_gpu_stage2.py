@@ -347,7 +347,7 @@ def test_knob_arguments():
     assert L.ht_set_knob(ht.KNOB_WAIT_POLLS, -1) == -2
     assert L.ht_set_knob(ht.KNOB_UPDATE_TILE_ROWS, 3) == -2
     assert L.ht_get_knob(ht.KNOB_UPDATE_TILE_ROWS) == 0
-    assert L.ht_set_knob(ht.KNOB_LOOKAHEAD, 2) == -2 and L.ht_set_knob(ht.KNOB_LOOKAHEAD, -1) == -2
+    assert L.ht_set_knob(ht.KNOB_LOOKAHEAD, 3) == -2 and L.ht_set_knob(ht.KNOB_LOOKAHEAD, -1) == -2
     assert L.ht_get_knob(ht.KNOB_LOOKAHEAD) == 1
 
 
@@ -355,7 +355,7 @@ def test_knob_arguments():
 
 def _with_lookahead(on, fn):
     ht = _ht()
-    old = ht.set_knob(ht.KNOB_LOOKAHEAD, 1 if on else 0)
+    old = ht.set_knob(ht.KNOB_LOOKAHEAD, 2 if on else 0)      # 2: also below the automatic size limit
     try:
         return fn()
     finally:
@@ -464,12 +464,14 @@ def test_lookahead_wait_give_up_is_reported():
     H, T = inputs.rht_pencil(n, r, 8)
     assert ht.stream_status() == 0
     old = ht.set_knob(ht.KNOB_WAIT_POLLS, 0)
+    old_la = ht.set_knob(ht.KNOB_LOOKAHEAD, 2)              # also below the automatic size limit
     try:
         Hd, Td = ht.colmajor(H), ht.colmajor(T)
         ht.stage2(Hd, Td, r, ht.colmajor(np.eye(n)), ht.colmajor(np.eye(n)))
         torch.cuda.synchronize()
     finally:
         ht.set_knob(ht.KNOB_WAIT_POLLS, old)
+        ht.set_knob(ht.KNOB_LOOKAHEAD, old_la)
     assert ht.stream_status() == 5
     assert ht.stream_status() == 0
     check_parity(H, T, r)

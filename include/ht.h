@@ -94,8 +94,8 @@ int ht_stage2_z_q(void *H, void *T, void *Q, void *Z,
  *     device it runs on until the process ends; the call allocates nothing
  *     (no hipMalloc/hipFree, no stream or event creation, no library routine
  *     that allocates).  Every size with ht_workspace_bytes(n, r, 0, 0) <=
- *     HT_NOALLOC_SCRATCH_BYTES - 256 fits (n <= 2895 at r = 32, 8975 at
- *     r = 16, 24522 at r = 8; the call takes one of the two reflector buffers
+ *     HT_NOALLOC_SCRATCH_BYTES - 256 fits (n <= 2832 at r = 32, 8398 at
+ *     r = 16, 20654 at r = 8; the call takes one of the two reflector buffers
  *     that figure includes, so somewhat larger n fit too); a call that does
  *     not fit returns HT_ERR_SCRATCH and enqueues nothing.
  *   - Every kernel runs on `stream` (Q and Z are not overlapped on a second

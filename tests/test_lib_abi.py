@@ -99,3 +99,25 @@ def test_batched_argument_errors_need_no_device():
     assert call(ld=arr(8, 4)) == -8
     assert call(q=arr(0, 5)) == -9                 # q > min(r, n-1)
     assert call(H=nul) == -2                        # NULL H[b] with n[b] > 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libht.so not built")
+def test_knobs_need_no_device():
+    """The process-wide knobs are host state: defaults, ranges and the
+    unknown-knob error, without a device."""
+    L = ctypes.CDLL(LIB)
+    L.ht_set_knob.restype = ctypes.c_int
+    L.ht_set_knob.argtypes = [ctypes.c_int, ctypes.c_int64]
+    L.ht_get_knob.restype = ctypes.c_int64
+    L.ht_get_knob.argtypes = [ctypes.c_int]
+    WAIT_POLLS, TILE_ROWS, LOOKAHEAD = 1, 2, 3
+    assert L.ht_get_knob(WAIT_POLLS) == 1 << 22
+    assert L.ht_get_knob(TILE_ROWS) == 0
+    assert L.ht_get_knob(LOOKAHEAD) == 1
+    assert L.ht_get_knob(0) == -1 and L.ht_get_knob(4) == -1
+    assert L.ht_set_knob(4, 0) == -1
+    for knob, bad in ((WAIT_POLLS, -1), (TILE_ROWS, 3), (LOOKAHEAD, 3), (LOOKAHEAD, -1)):
+        assert L.ht_set_knob(knob, bad) == -2
+        assert L.ht_get_knob(knob) in (1 << 22, 0, 1)         # unchanged
+    for v in (0, 2, 1):
+        assert L.ht_set_knob(LOOKAHEAD, v) == 0 and L.ht_get_knob(LOOKAHEAD) == v

@@ -368,6 +368,7 @@ def bench_stage1(args):
     import paper_2301_07964_amd as ht
     from paper_2301_07964_amd import inputs
     n, r, cplx = args.n, args.r, args.complex
+    ht.set_knob(ht.KNOB_LOOKAHEAD, args.lookahead)
     A, B = inputs.dense_pencil(n, seed=args.seed, complex_=cplx)
     A0, B0 = ht.colmajor(A), ht.colmajor(B)
     del A, B
@@ -404,7 +405,7 @@ def bench_stage1(args):
                       "vs_baseline": None, "dtype": "c128" if cplx else "f64", "data": "synthetic",
                       "config": {"workload": f"stage one of a dense {'complex128' if cplx else 'FP64'} pencil, n={n}, "
                                              f"r={r} (p={p}), Q and Z accumulated, seed {args.seed}",
-                                 "n": n, "r": r, "p": p},
+                                 "n": n, "r": r, "p": p, "lookahead": args.lookahead},
                       "flops_per_step": flops, "check": check}))
 
 
@@ -479,7 +480,7 @@ def main():
                     help="single: 1 (the default) overlaps each group's generation with the previous group's left "
                          "pass from n = 1024 on, 2 at every n, 0 runs the groups one after the other (for "
                          "profilers that run one kernel at a time, where the overlapped schedule would wait on a "
-                         "kernel that cannot start)")
+                         "kernel that cannot start); stage1: the same values switch the three-stream schedule")
     ap.add_argument("--wait-polls", type=int, default=0,
                     help="single: polls before a device-side wait gives up (0: the library default)")
     args = ap.parse_args()

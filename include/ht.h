@@ -163,6 +163,13 @@ int ht_stream_status(void *stream);
  *     and complex pencils with r in {4, 8, 16, 32} on the allocating entry
  *     points, while no lookahead call on another stream of the device is
  *     still running (otherwise that call runs its groups in sequence).
+ *     The same values switch stage one (ht_rhess*) to its three-stream
+ *     schedule (Section 2.3's task split): the Q and Z passes, and each
+ *     block's pass over the rows of B that the following block factors do
+ *     not read, run on two streams the library keeps beside the caller's
+ *     (per device and caller stream); the call is still ordered on the
+ *     caller's stream, and its results are bitwise those of the one-stream
+ *     schedule.
  */
 #define HT_KNOB_WAIT_POLLS 1
 #define HT_KNOB_UPDATE_TILE_ROWS 2
@@ -224,7 +231,8 @@ int ht_batched_set_tuning(int64_t entries, const int64_t *n_max, const int64_t *
  *   below the r-th subdiagonal) and B upper triangular (exact zeros below);
  *   Q <- Q*Q1, Z <- Z*Z1 with (A_in, B_in) = Q1 (A_out, B_out) Z1^H, where
  *   Q1 e1 is the first column of the QR factor of B and Z1 e1 = e1.  Q, Z
- *   may be NULL.  The output depends on (n_b, p); the HT form reached after
+ *   may be NULL; the four matrices must not overlap.  The output depends
+ *   on (n_b, p); the HT form reached after
  *   ht_stage2 does not (up to the unimodular diagonal scaling that the
  *   reflector conventions fix).
  * Errors as ht_stage2 (-5 n, -6 r, -7 ld, -1/-2 NULL A/B, -8 p);

@@ -19,7 +19,9 @@
 //                the exact zeros of the block's first nb columns; after the
 //                last block, A and Z receive all blocks' P_t (chain kernels).
 // The QR of B uses the same block-QR and chain kernels (blocks start at the
-// panel's first row).  All arithmetic is FP64 / complex128.
+// panel's first row).  All arithmetic is FP64 / complex128.  With the
+// overlapped schedule (below) the Q and Z passes and the far rows of each
+// block's pass over B run on two more streams beside the caller's.
 #include "ht_common.hpp"
 #include "ht_workspace.hpp"
 #include "ht.h"
@@ -27,6 +29,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace ht {
 
@@ -461,13 +467,98 @@ static size_t s1_workspace_bytes(int64_t n, int64_t nb, int64_t p, size_t elem)
     return 2 * ((size_t)maxblk * p * nb * nb * elem + (size_t)maxblk * nb * elem) + 1024;
 }
 
+// ------------------------------------------------------------ overlap
+// The tasks of parallel stage one (Section 2.3): generating a panel's left
+// reflectors (block QRs) and right reflectors (the per-block factors with
+// their pass over B) stay on the caller's stream; applying them to Q (left)
+// and Z (right) depends on nothing else, so those passes run on a second
+// stream `qz` beside the rest.  In each block's pass over B only the rows that
+// the next factors read (from a lower bound L down the chain) stay on the
+// caller's stream; the rows above L go to a third stream `far`.  L is moved
+// down once every kS1Chunk blocks, and only then does the caller's stream wait
+// for the far rows already queued: adjacent blocks share columns, so rows
+// handed to `far` for block k+1 must be finished before the caller's stream
+// updates them for block k.  Every entry receives the same operations in the
+// same order as in the one-stream schedule, so the results are bitwise equal.
+constexpr int64_t kS1Chunk = 8;        // blocks per position of the bound L
+constexpr int64_t kS1OverlapMinN = 1024;
+
+struct S1Ctx {
+    hipStream_t far = nullptr, qz = nullptr;
+    hipEvent_t fac = nullptr, far_done = nullptr, gl = nullptr, lq = nullptr, gr = nullptr, rz = nullptr;
+    bool ok = false;
+};
+static std::mutex g_s1_mu;
+static std::map<std::pair<int, hipStream_t>, S1Ctx> g_s1;
+
+static S1Ctx *s1_ctx(hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_s1_mu);
+    S1Ctx &c = g_s1[{dev, st}];
+    if (c.ok) return &c;
+    if (!c.far && hipStreamCreateWithFlags(&c.far, hipStreamNonBlocking) != hipSuccess) { c.far = nullptr; return nullptr; }
+    if (!c.qz && hipStreamCreateWithFlags(&c.qz, hipStreamNonBlocking) != hipSuccess) { c.qz = nullptr; return nullptr; }
+    hipEvent_t *ev[] = {&c.fac, &c.far_done, &c.gl, &c.lq, &c.gr, &c.rz};
+    for (hipEvent_t *e : ev)
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { *e = nullptr; return nullptr; }
+    c.ok = true;
+    return &c;
+}
+
+// Which events of the context this call has recorded (a stream waits only for
+// an event recorded earlier in the same call).
+struct S1Sched {
+    S1Ctx *c = nullptr;                // null: everything on the caller's stream
+    hipStream_t st = nullptr;
+    bool far_rec = false, lq_rec = false, rz_rec = false;
+    hipStream_t qz_stream() const { return c ? c->qz : st; }
+    int record(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s) == hipSuccess ? 0 : 1; }
+    int wait(hipStream_t s, hipEvent_t e) { return hipStreamWaitEvent(s, e, 0) == hipSuccess ? 0 : 1; }
+    // the caller's stream waits for everything queued on the other two
+    int join()
+    {
+        if (!c) return 0;
+        int rc = 0;
+        if (hipEventRecord(c->far_done, c->far) != hipSuccess || hipStreamWaitEvent(st, c->far_done, 0) != hipSuccess) rc = 1;
+        if (hipEventRecord(c->rz, c->qz) != hipSuccess || hipStreamWaitEvent(st, c->rz, 0) != hipSuccess) rc = 1;
+        return rc;
+    }
+};
+
+template <class S>
+static int right_chain(S *X, int64_t ld, const Blocks &bl, int nb, const S *V, const S *tau, int64_t rfirst,
+                       int64_t rlast, hipStream_t s)
+{
+    if (rlast < rfirst) return 0;
+    // rows rfirst..rlast: the kernel's rows are relative to X, its columns absolute
+    const int64_t rows = rlast - rfirst + 1;
+    hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, s,
+                       X + rfirst, ld, bl, nb, V, tau, rows - 1);
+    return launch_check("k_s1_right_chain");
+}
+
 template <class S>
 static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blocks &bl, int64_t c0, int nc,
-                      S *V, S *tau, int64_t a2first, int64_t b2first, int b2from_block, hipStream_t st)
+                      S *V, S *tau, int64_t a2first, int64_t b2first, int b2from_block, S1Sched &sc)
 {
     int rc;
+    const hipStream_t st = sc.st;
+    // the previous panel's Q pass reads V and tau
+    if (sc.lq_rec && (rc = sc.wait(st, sc.c->lq))) return rc;
     hipLaunchKernelGGL(k_s1_block_qr<S>, dim3(1), dim3(256), 0, st, X, ld, bl, c0, nc, V, tau);
     if ((rc = launch_check("k_s1_block_qr"))) return rc;
+    if (Q && sc.c) {
+        if ((rc = sc.record(sc.c->gl, st)) || (rc = sc.wait(sc.c->qz, sc.c->gl))) return rc;
+    }
+    if (Q) {
+        if ((rc = right_chain<S>(Q, ld, bl, nc, V, tau, 0, n - 1, sc.qz_stream()))) return rc;
+        if (sc.c) {
+            if ((rc = sc.record(sc.c->lq, sc.c->qz))) return rc;
+            sc.lq_rec = true;
+        }
+    }
     // X's own columns right of the panel (or A for the QR of B)
     if (A2 && a2first <= n - 1) {
         const int64_t ncols = n - a2first;
@@ -476,15 +567,92 @@ static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blo
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
     if (B2 && b2first <= n - 1) {
+        // the previous panel's far rows of B
+        if (sc.far_rec && (rc = sc.wait(st, sc.c->far_done))) return rc;
         const int64_t ncols = n - b2first;
         hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, B2, ld, bl, nc,
                            (const S *)V, (const S *)tau, b2first, n - 1, b2from_block);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
     }
-    if (Q) {
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, Q, ld, bl, nc,
-                           (const S *)V, (const S *)tau, n - 1);
-        if ((rc = launch_check("k_s1_right_chain"))) return rc;
+    return 0;
+}
+
+// Right phase of one panel: per block from the bottom, the factor, its pass
+// over rows 0..r1(k) of B (rows from L(k) on the caller's stream, the rest on
+// `far`), the exact zeros; then A on the caller's stream and Z on `qz`.
+template <class S>
+static int right_phase(S *A, S *B, S *Z, int64_t ld, int64_t n, const Blocks &bl, int nb, S *VR, S *TR, S1Sched &sc)
+{
+    int rc;
+    const hipStream_t st = sc.st;
+    const int64_t bm = bl.bm, nblk = bl.nblk;
+    // the previous panel's Z pass reads VR and TR
+    if (sc.rz_rec && (rc = sc.wait(st, sc.c->rz))) return rc;
+    int64_t Lprev = -1;
+    for (int64_t k = nblk - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(k_s1_right_factor<S>, dim3(1), dim3(256), 0, st, (const S *)B, ld, bl, k, nb, VR, TR);
+        if ((rc = launch_check("k_s1_right_factor"))) return rc;
+        const S *Vk = VR + k * bm * nb, *Tk = TR + k * nb;
+        const Blocks one_blk{bl.r0(k), bl.step, bm, 1, n};
+        // L(k) <= r0(k-1): the factor of block k-1 reads rows r0(k-1)..r1(k-1)
+        const int64_t kc = (k / kS1Chunk) * kS1Chunk;
+        const int64_t L = sc.c ? bl.r0(kc > 0 ? kc - 1 : 0) : 0;
+        if (sc.c) {
+            if ((rc = sc.record(sc.c->fac, st))) return rc;
+            // rows L..L(k+1)-1 were handed to `far` for block k+1
+            if (Lprev >= 0 && L < Lprev && (rc = sc.wait(st, sc.c->far_done))) return rc;
+        }
+        if ((rc = right_chain<S>(B, ld, one_blk, nb, Vk, Tk, L, bl.r1(k), st))) return rc;
+        hipLaunchKernelGGL(k_s1_zero_block<S>, dim3(1), dim3(256), 0, st, B, ld, bl, k, nb);
+        if ((rc = launch_check("k_s1_zero_block"))) return rc;
+        if (sc.c && L > 0) {
+            if ((rc = sc.wait(sc.c->far, sc.c->fac))) return rc;
+            if ((rc = right_chain<S>(B, ld, one_blk, nb, Vk, Tk, 0, L - 1, sc.c->far))) return rc;
+            if ((rc = sc.record(sc.c->far_done, sc.c->far))) return rc;
+            sc.far_rec = true;
+        }
+        Lprev = L;
+    }
+    if (Z) {
+        if (sc.c) {
+            if ((rc = sc.record(sc.c->gr, st)) || (rc = sc.wait(sc.c->qz, sc.c->gr))) return rc;
+        }
+        if ((rc = right_chain<S>(Z, ld, bl, nb, VR, TR, 0, n - 1, sc.qz_stream()))) return rc;
+        if (sc.c) {
+            if ((rc = sc.record(sc.c->rz, sc.c->qz))) return rc;
+            sc.rz_rec = true;
+        }
+    }
+    return right_chain<S>(A, ld, bl, nb, VR, TR, 0, n - 1, st);
+}
+
+template <class S>
+static int rhess_body(S *A, S *B, S *Q, S *Z, int64_t n, int64_t nb, int64_t p, int64_t ld, S *VL, S *TL, S *VR,
+                      S *TR, S1Sched &sc)
+{
+    int rc = 0;
+    const int64_t bm = p * nb;
+    // 1. QR of B (panels of nb columns, blocks from the panel's first row)
+    for (int64_t c0 = 0; c0 + 1 < n; c0 += nb) {
+        const int nc = (int)i64min(nb, n - c0);
+        const int64_t rows = n - c0;
+        const int64_t nblk = rows <= bm ? 1 : 1 + (rows - bm + (p - 1) * nb - 1) / ((p - 1) * nb);
+        const Blocks bl{c0, (p - 1) * nb, bm, nblk, n};
+        // B is dense here: every block's reflectors reach all trailing columns
+        if ((rc = left_phase<S>(B, A, B, Q, ld, n, bl, c0, nc, VL, TL, 0, c0 + nc, 0, sc))) return rc;
+    }
+    // 2. panels of stage one (1-based j = 1, 1+nb, ...; 0-based first column j-1)
+    for (int64_t j = 1; j <= n - 2; j += nb) {
+        const int64_t j2 = i64min(n, j + nb - 1);
+        const int64_t num = n - nb - j + 1;
+        if (num <= 0) break;
+        const int64_t nblk = (num + (p - 1) * nb - 1) / ((p - 1) * nb);
+        const Blocks bl{j + nb - 1, (p - 1) * nb, bm, nblk, n};
+        const int nc = (int)(j2 - j + 1);
+        // left: QR of the panel blocks; A right of the panel, B from each block's first column, Q
+        if ((rc = left_phase<S>(A, A, B, Q, ld, n, bl, j - 1, nc, VL, TL, j2, bl.r0(0), 1, sc))) return rc;
+        // right: per block from the bottom; then A and Z
+        if ((rc = right_phase<S>(A, B, Z, ld, n, bl, (int)nb, VR, TR, sc))) return rc;
     }
     return 0;
 }
@@ -512,47 +680,20 @@ static int rhess_impl(S *A, S *B, S *Q, S *Z, int64_t n, int64_t r, int64_t ld, 
     unsigned char *ws = (unsigned char *)workspace_get(s1_workspace_bytes(n, nb, p, sizeof(S)), st, &rc);
     if (!ws) return rc;
     S *VL = (S *)ws, *TL = (S *)(ws + vb), *VR = (S *)(ws + vb + tb), *TR = (S *)(ws + 2 * vb + tb);
-    // 1. QR of B (panels of nb columns, blocks from the panel's first row)
-    for (int64_t c0 = 0; c0 + 1 < n; c0 += nb) {
-        const int nc = (int)i64min(nb, n - c0);
-        const int64_t rows = n - c0;
-        const int64_t nblk = rows <= bm ? 1 : 1 + (rows - bm + (p - 1) * nb - 1) / ((p - 1) * nb);
-        const Blocks bl{c0, (p - 1) * nb, bm, nblk, n};
-        // B is dense here: every block's reflectors reach all trailing columns
-        if ((rc = left_phase<S>(B, A, B, Q, ld, n, bl, c0, nc, VL, TL, 0, c0 + nc, 0, st))) return rc;
+    S1Sched sc;
+    sc.st = st;
+    const int64_t knob_la = knob(HT_KNOB_LOOKAHEAD);
+    if (knob_la == 2 || (knob_la == 1 && n >= kS1OverlapMinN)) {
+        sc.c = s1_ctx(st);
+        // (every launch on the other streams waits for an event recorded on
+        // the caller's stream after the work queued there before this call)
+        if (!sc.c) { (void)hipGetLastError(); return 1; }
     }
-    // 2. panels of stage one (1-based j = 1, 1+nb, ...; 0-based first column j-1)
-    for (int64_t j = 1; j <= n - 2; j += nb) {
-        const int64_t j2 = i64min(n, j + nb - 1);
-        const int64_t num = n - nb - j + 1;
-        if (num <= 0) break;
-        const int64_t nblk = (num + (p - 1) * nb - 1) / ((p - 1) * nb);
-        const Blocks bl{j + nb - 1, (p - 1) * nb, bm, nblk, n};
-        const int nc = (int)(j2 - j + 1);
-        // left: QR of the panel blocks; A right of the panel, B from each block's first column, Q
-        if ((rc = left_phase<S>(A, A, B, Q, ld, n, bl, j - 1, nc, VL, TL, j2, bl.r0(0), 1, st))) return rc;
-        // right: per block from the bottom
-        for (int64_t k = nblk - 1; k >= 0; --k) {
-            hipLaunchKernelGGL(k_s1_right_factor<S>, dim3(1), dim3(256), 0, st, (const S *)B, ld, bl, k, (int)nb, VR, TR);
-            if ((rc = launch_check("k_s1_right_factor"))) return rc;
-            // B(0:i2, block k columns) <- B P_0 ... P_{nb-1}: the row chain with this block only
-            const int64_t rows = bl.r1(k) + 1;
-            const Blocks one_blk{bl.r0(k), bl.step, bm, 1, n};
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((rows + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, B, ld, one_blk,
-                               (int)nb, (const S *)(VR + k * bm * nb), (const S *)(TR + k * nb), rows - 1);
-            if ((rc = launch_check("k_s1_right_chain"))) return rc;
-            hipLaunchKernelGGL(k_s1_zero_block<S>, dim3(1), dim3(256), 0, st, B, ld, bl, k, (int)nb);
-            if ((rc = launch_check("k_s1_zero_block"))) return rc;
-        }
-        hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, A, ld, bl, (int)nb,
-                           (const S *)VR, (const S *)TR, n - 1);
-        if ((rc = launch_check("k_s1_right_chain"))) return rc;
-        if (Z) {
-            hipLaunchKernelGGL(k_s1_right_chain<S>, dim3((unsigned)((n + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, Z, ld, bl, (int)nb,
-                               (const S *)VR, (const S *)TR, n - 1);
-            if ((rc = launch_check("k_s1_right_chain"))) return rc;
-        }
-    }
+    rc = rhess_body<S>(A, B, Q, Z, n, nb, p, ld, VL, TL, VR, TR, sc);
+    // on every path, the caller's stream covers the work queued on the others
+    const int jrc = sc.join();
+    if (rc) return rc;
+    if (jrc) return jrc;
     hipLaunchKernelGGL(k_s1_zero_pattern<S>, dim3((unsigned)n), dim3(256), 0, st, A, B, ld, n, nb);
     return launch_check("k_s1_zero_pattern");
 }

@@ -115,6 +115,53 @@ def test_rhess_invariants_large(n, r):
     assert max(vals) <= 100 * n * EPS, vals
 
 
+def _with_overlap(on, fn):
+    ht = _ht()
+    old = ht.set_knob(ht.KNOB_LOOKAHEAD, 2 if on else 0)      # 2: also below the automatic size limit
+    try:
+        return fn()
+    finally:
+        ht.set_knob(ht.KNOB_LOOKAHEAD, old)
+
+
+@pytest.mark.parametrize("n,r,p,cplx,withq,withz", [
+    (300, 4, 0, False, True, True), (500, 16, 0, False, True, True), (257, 8, 3, False, True, True),
+    (700, 32, 2, False, True, True), (400, 16, 2, True, True, True), (333, 8, 0, True, True, True),
+    (300, 16, 0, False, False, True), (300, 16, 0, False, True, False), (300, 16, 0, False, False, False),
+    (1100, 16, 0, False, True, True), (40, 16, 0, False, True, True), (3, 1, 0, False, True, True)])
+def test_rhess_overlap_is_bitwise_the_one_stream_order(n, r, p, cplx, withq, withz):
+    """The three-stream schedule of stage one (Q and Z passes, and the rows of
+    B that the next block factors do not read, on streams of their own) gives
+    the same bits as the one-stream schedule.  The call runs on a side stream
+    and the results are copied on that stream right after it, so a missing
+    join of the other streams would show as a stale copy."""
+    ht = _ht()
+    print(f"[rhess overlap] n={n} r={r} p={p} complex={cplx} Q={withq} Z={withz}", flush=True)
+    A, B = inputs.dense_pencil(n, seed=3 * n + r, complex_=cplx)
+
+    def run():
+        Ad, Bd = ht.colmajor(A), ht.colmajor(B)
+        Qd = ht.colmajor(np.eye(n, dtype=A.dtype)) if withq else None
+        Zd = ht.colmajor(np.eye(n, dtype=A.dtype)) if withz else None
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ht.rhess(Ad, Bd, r, Qd, Zd, p=p)
+            outs = [x for x in (Ad, Bd, Qd, Zd) if x is not None]
+            snap = [x.clone() for x in outs]
+        torch.cuda.synchronize()
+        for a, b in zip(outs, snap):
+            assert torch.equal(a, b)
+        return [ht.to_numpy(x) for x in outs]
+
+    on = _with_overlap(True, run)
+    off = _with_overlap(False, run)
+    for a, b in zip(on, off):
+        assert np.array_equal(a, b)
+    if withq and withz:
+        _check_invariants(A, B, on[0], on[1], on[2], on[3], r)
+
+
 def test_rhess_invalid_arguments():
     ht = _ht()
     A = ht.colmajor(np.eye(64))

@@ -471,8 +471,10 @@ static size_t s1_workspace_bytes(int64_t n, int64_t nb, int64_t p, size_t elem)
 // The tasks of parallel stage one (Section 2.3): generating a panel's left
 // reflectors (block QRs) and right reflectors (the per-block factors with
 // their pass over B) stay on the caller's stream; applying them to Q (left)
-// and Z (right) depends on nothing else, so those passes run on a second
-// stream `qz` beside the rest.  In each block's pass over B only the rows that
+// and Z (right) depends on nothing else, and the left pass over A only has to
+// precede the right pass over A and the next block QR, so those three passes
+// run on a second stream `qz` beside the rest (during the QR of B, the pass
+// over A runs on the third stream, idle then).  In each block's pass over B only the rows that
 // the next factors read (from a lower bound L down the chain) stay on the
 // caller's stream; the rows above L go to a third stream `far`.  L is moved
 // down once every kS1Chunk blocks, and only then does the caller's stream wait
@@ -485,7 +487,7 @@ constexpr int64_t kS1OverlapMinN = 1024;
 
 struct S1Ctx {
     hipStream_t far = nullptr, qz = nullptr;
-    hipEvent_t fac = nullptr, far_done = nullptr, gl = nullptr, lq = nullptr, gr = nullptr, rz = nullptr;
+    hipEvent_t fac = nullptr, far_done = nullptr, gl = nullptr, lq = nullptr, gr = nullptr, rz = nullptr, fa = nullptr;
     bool ok = false;
 };
 static std::mutex g_s1_mu;
@@ -500,7 +502,7 @@ static S1Ctx *s1_ctx(hipStream_t st)
     if (c.ok) return &c;
     if (!c.far && hipStreamCreateWithFlags(&c.far, hipStreamNonBlocking) != hipSuccess) { c.far = nullptr; return nullptr; }
     if (!c.qz && hipStreamCreateWithFlags(&c.qz, hipStreamNonBlocking) != hipSuccess) { c.qz = nullptr; return nullptr; }
-    hipEvent_t *ev[] = {&c.fac, &c.far_done, &c.gl, &c.lq, &c.gr, &c.rz};
+    hipEvent_t *ev[] = {&c.fac, &c.far_done, &c.gl, &c.lq, &c.gr, &c.rz, &c.fa};
     for (hipEvent_t *e : ev)
         if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) { *e = nullptr; return nullptr; }
     c.ok = true;
@@ -512,7 +514,7 @@ static S1Ctx *s1_ctx(hipStream_t st)
 struct S1Sched {
     S1Ctx *c = nullptr;                // null: everything on the caller's stream
     hipStream_t st = nullptr;
-    bool far_rec = false, lq_rec = false, rz_rec = false;
+    bool far_rec = false, lq_rec = false, rz_rec = false, fa_rec = false;
     hipStream_t qz_stream() const { return c ? c->qz : st; }
     int record(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s) == hipSuccess ? 0 : 1; }
     int wait(hipStream_t s, hipEvent_t e) { return hipStreamWaitEvent(s, e, 0) == hipSuccess ? 0 : 1; }
@@ -541,30 +543,44 @@ static int right_chain(S *X, int64_t ld, const Blocks &bl, int nb, const S *V, c
 
 template <class S>
 static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blocks &bl, int64_t c0, int nc,
-                      S *V, S *tau, int64_t a2first, int64_t b2first, int b2from_block, S1Sched &sc)
+                      S *V, S *tau, int64_t a2first, int64_t b2first, int b2from_block, bool qr_of_b, S1Sched &sc)
 {
     int rc;
     const hipStream_t st = sc.st;
-    // the previous panel's Q pass reads V and tau
+    // the previous panel's passes over Q and A read V and tau
     if (sc.lq_rec && (rc = sc.wait(st, sc.c->lq))) return rc;
+    if (sc.fa_rec) {
+        if ((rc = sc.wait(st, sc.c->fa))) return rc;
+        sc.fa_rec = false;
+    }
     hipLaunchKernelGGL(k_s1_block_qr<S>, dim3(1), dim3(256), 0, st, X, ld, bl, c0, nc, V, tau);
     if ((rc = launch_check("k_s1_block_qr"))) return rc;
-    if (Q && sc.c) {
-        if ((rc = sc.record(sc.c->gl, st)) || (rc = sc.wait(sc.c->qz, sc.c->gl))) return rc;
-    }
+    // Q and the columns of A right of the panel (or all of A for the QR of B):
+    // only the right pass over A and the next block QR wait for them.  The
+    // pass over A runs on `qz` after Q's, except in the QR of B, where `far`
+    // is idle and takes it (no factor chain to hide the two passes behind)
+    const bool has_a = A2 && a2first <= n - 1;
+    const hipStream_t qs = sc.qz_stream();
+    const hipStream_t as = sc.c ? (qr_of_b ? sc.c->far : sc.c->qz) : st;
+    if (sc.c && (Q || has_a) && (rc = sc.record(sc.c->gl, st))) return rc;
     if (Q) {
-        if ((rc = right_chain<S>(Q, ld, bl, nc, V, tau, 0, n - 1, sc.qz_stream()))) return rc;
-        if (sc.c) {
-            if ((rc = sc.record(sc.c->lq, sc.c->qz))) return rc;
-            sc.lq_rec = true;
-        }
+        if (sc.c && (rc = sc.wait(qs, sc.c->gl))) return rc;
+        if ((rc = right_chain<S>(Q, ld, bl, nc, V, tau, 0, n - 1, qs))) return rc;
     }
-    // X's own columns right of the panel (or A for the QR of B)
-    if (A2 && a2first <= n - 1) {
+    if (has_a) {
+        if (sc.c && (rc = sc.wait(as, sc.c->gl))) return rc;
         const int64_t ncols = n - a2first;
-        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, st, A2, ld, bl, nc,
+        hipLaunchKernelGGL(k_s1_left_chain<S>, dim3((unsigned)((ncols + kS1Cols - 1) / kS1Cols)), dim3(kS1ChainThreads), 0, as, A2, ld, bl, nc,
                            (const S *)V, (const S *)tau, a2first, n - 1, 0);
         if ((rc = launch_check("k_s1_left_chain"))) return rc;
+    }
+    if (sc.c && (Q || (has_a && as == sc.c->qz))) {
+        if ((rc = sc.record(sc.c->lq, qs))) return rc;
+        sc.lq_rec = true;
+    }
+    if (sc.c && has_a && as == sc.c->far) {
+        if ((rc = sc.record(sc.c->fa, as))) return rc;
+        sc.fa_rec = true;
     }
     if (B2 && b2first <= n - 1) {
         // the previous panel's far rows of B
@@ -579,7 +595,8 @@ static int left_phase(S *X, S *A2, S *B2, S *Q, int64_t ld, int64_t n, const Blo
 
 // Right phase of one panel: per block from the bottom, the factor, its pass
 // over rows 0..r1(k) of B (rows from L(k) on the caller's stream, the rest on
-// `far`), the exact zeros; then A on the caller's stream and Z on `qz`.
+// `far`), the exact zeros; then Z on `qz` and A on the caller's stream (after
+// the panel's left pass over A).
 template <class S>
 static int right_phase(S *A, S *B, S *Z, int64_t ld, int64_t n, const Blocks &bl, int nb, S *VR, S *TR, S1Sched &sc)
 {
@@ -623,6 +640,8 @@ static int right_phase(S *A, S *B, S *Z, int64_t ld, int64_t n, const Blocks &bl
             sc.rz_rec = true;
         }
     }
+    // the left pass over A of this panel
+    if (sc.lq_rec && (rc = sc.wait(st, sc.c->lq))) return rc;
     return right_chain<S>(A, ld, bl, nb, VR, TR, 0, n - 1, st);
 }
 
@@ -639,7 +658,7 @@ static int rhess_body(S *A, S *B, S *Q, S *Z, int64_t n, int64_t nb, int64_t p, 
         const int64_t nblk = rows <= bm ? 1 : 1 + (rows - bm + (p - 1) * nb - 1) / ((p - 1) * nb);
         const Blocks bl{c0, (p - 1) * nb, bm, nblk, n};
         // B is dense here: every block's reflectors reach all trailing columns
-        if ((rc = left_phase<S>(B, A, B, Q, ld, n, bl, c0, nc, VL, TL, 0, c0 + nc, 0, sc))) return rc;
+        if ((rc = left_phase<S>(B, A, B, Q, ld, n, bl, c0, nc, VL, TL, 0, c0 + nc, 0, true, sc))) return rc;
     }
     // 2. panels of stage one (1-based j = 1, 1+nb, ...; 0-based first column j-1)
     for (int64_t j = 1; j <= n - 2; j += nb) {
@@ -650,7 +669,7 @@ static int rhess_body(S *A, S *B, S *Q, S *Z, int64_t n, int64_t nb, int64_t p, 
         const Blocks bl{j + nb - 1, (p - 1) * nb, bm, nblk, n};
         const int nc = (int)(j2 - j + 1);
         // left: QR of the panel blocks; A right of the panel, B from each block's first column, Q
-        if ((rc = left_phase<S>(A, A, B, Q, ld, n, bl, j - 1, nc, VL, TL, j2, bl.r0(0), 1, sc))) return rc;
+        if ((rc = left_phase<S>(A, A, B, Q, ld, n, bl, j - 1, nc, VL, TL, j2, bl.r0(0), 1, false, sc))) return rc;
         // right: per block from the bottom; then A and Z
         if ((rc = right_phase<S>(A, B, Z, ld, n, bl, (int)nb, VR, TR, sc))) return rc;
     }

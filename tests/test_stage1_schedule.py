@@ -5,9 +5,12 @@ paper (Section 2.3, the dependency graph of its tasks): generating a panel's
 left reflectors (block QRs), applying them to A, B and Q; generating the
 right reflectors block by block (each block's factor and its pass over B),
 applying them to A and Z.  With the overlapped schedule the library runs the
-Q and Z passes on a second stream and the rows of B above a bound L (that the
-next factors do not read) on a third; L moves down once every `chunk` blocks,
-and only then does the caller's stream wait for the far rows.
+left passes over Q and A and the right pass over Z on a second stream (only
+the right pass over A and the next block QRs wait for the pass over A; during
+the QR of B the pass over A runs on the third), and the rows of B above a
+bound L (that the next factors do not read) on a third;
+L moves down once every `chunk` blocks, and only then does the caller's stream
+wait for the far rows.
 
 This test restates, per launch, the entries (rectangles) of A, B, Q, Z and of
 the reflector buffers that the launch reads and writes, and the event records
@@ -77,30 +80,42 @@ def stage_one_schedule(n, nb, p, overlap, chunk=8, with_q=True, with_z=True, ski
     ALL = lambda mat: (mat, 0, n - 1, 0, n - 1)
     m.launch("st", writes=[ALL(x) for x in "ABQZ"])            # the caller fills the inputs
     st = "st"
-    rec = {"far": False, "lq": False, "rz": False}
+    rec = {"far": False, "lq": False, "rz": False, "fa": False}
     qs = "qz" if overlap else st
 
     def rows_of(bl):
         return bl.r0(0), bl.r1(bl.nblk - 1)
 
-    def left_phase(X, A2, B2, bl, c0, nc, a2first, b2first, from_block):
+    def left_phase(X, A2, B2, bl, c0, nc, a2first, b2first, from_block, qr_of_b):
         if rec["lq"] and "lq" not in skip:
             m.wait(st, "lq")
+        if rec["fa"]:
+            if "fa" not in skip:
+                m.wait(st, "fa")
+            rec["fa"] = False
         ra, rb = rows_of(bl)
         m.launch(st, reads=[(X, ra, rb, c0, c0 + nc - 1)], writes=[(X, ra, rb, c0, c0 + nc - 1), ("VL", 0, 0, 0, 0)])
+        has_a = a2first <= n - 1
+        # the pass over A: on `far` during the QR of B (idle then), else on `qz`
+        sa = ("far" if qr_of_b else "qz") if overlap else st
+        if overlap and (with_q or has_a):
+            m.record("gl", st)
         if with_q:
-            if overlap:
-                m.record("gl", st)
-                if "q_start" not in skip:
-                    m.wait("qz", "gl")
+            if overlap and "q_start" not in skip:
+                m.wait("qz", "gl")
             cells = ("Q", 0, n - 1, ra, rb)
             m.launch(qs, reads=[cells, ("VL", 0, 0, 0, 0)], writes=[cells])
-            if overlap:
-                m.record("lq", "qz")
-                rec["lq"] = True
-        if a2first <= n - 1:
+        if has_a:
+            if overlap and "a_start" not in skip:
+                m.wait(sa, "gl")
             cells = (A2, ra, rb, a2first, n - 1)
-            m.launch(st, reads=[cells, ("VL", 0, 0, 0, 0)], writes=[cells])
+            m.launch(sa, reads=[cells, ("VL", 0, 0, 0, 0)], writes=[cells])
+        if overlap and (with_q or (has_a and sa == "qz")):
+            m.record("lq", "qz")
+            rec["lq"] = True
+        if overlap and has_a and sa == "far":
+            m.record("fa", "far")
+            rec["fa"] = True
         if b2first <= n - 1:
             if rec["far"] and "far_lb" not in skip:
                 m.wait(st, "far_done")
@@ -146,6 +161,8 @@ def stage_one_schedule(n, nb, p, overlap, chunk=8, with_q=True, with_z=True, ski
             if overlap:
                 m.record("rz", "qz")
                 rec["rz"] = True
+        if rec["lq"] and "la" not in skip:
+            m.wait(st, "lq")
         m.launch(st, reads=[("A", 0, n - 1, ra, rb), vr], writes=[("A", 0, n - 1, ra, rb)])
 
     c0 = 0
@@ -153,7 +170,7 @@ def stage_one_schedule(n, nb, p, overlap, chunk=8, with_q=True, with_z=True, ski
         nc = min(nb, n - c0)
         rows = n - c0
         nblk = 1 if rows <= bm else 1 + (rows - bm + (p - 1) * nb - 1) // ((p - 1) * nb)
-        left_phase("B", "A", "B", Blocks(c0, (p - 1) * nb, bm, nblk, n), c0, nc, 0, c0 + nc, False)
+        left_phase("B", "A", "B", Blocks(c0, (p - 1) * nb, bm, nblk, n), c0, nc, 0, c0 + nc, False, True)
         c0 += nb
     j = 1
     while j <= n - 2:                                          # panels
@@ -163,7 +180,7 @@ def stage_one_schedule(n, nb, p, overlap, chunk=8, with_q=True, with_z=True, ski
             break
         nblk = (num + (p - 1) * nb - 1) // ((p - 1) * nb)
         bl = Blocks(j + nb - 1, (p - 1) * nb, bm, nblk, n)
-        left_phase("A", "A", "B", bl, j - 1, j2 - j + 1, j2, bl.r0(0), True)
+        left_phase("A", "A", "B", bl, j - 1, j2 - j + 1, j2, bl.r0(0), True, False)
         right_phase(bl)
         j += nb
     if overlap and "join" not in skip:
@@ -224,7 +241,7 @@ def test_one_stream_schedule_is_trivially_ordered():
     assert m.count["far"] == 0 and m.count["qz"] == 0 and races(m) == []
 
 
-@pytest.mark.parametrize("wait", ["bound", "lq", "rz", "far_lb", "join", "far_start", "z_start", "q_start"])
+@pytest.mark.parametrize("wait", ["bound", "lq", "rz", "far_lb", "join", "far_start", "z_start", "q_start", "la", "fa", "a_start"])
 def test_model_detects_each_missing_wait(wait):
     """Every wait of the schedule is needed: without any one of them some
     launch races with another."""

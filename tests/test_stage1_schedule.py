@@ -258,3 +258,15 @@ def test_the_bound_moves_once_per_chunk():
     blocks = sum(1 for op in m.ops if op[0] == "far" and op[2][1])
     panels = len([1 for j in range(1, n - 1, nb) if n - nb - j + 1 > 0])
     assert blocks > 8 * panels and waits < blocks / 4
+
+
+def test_model_uses_the_library_chunk_length():
+    """The model's default chunk is the one the library compiles in."""
+    import inspect
+    import re
+    from pathlib import Path
+    src = (Path(__file__).resolve().parents[1] / "paper_2301_07964_amd" / "csrc" / "ht_stage1.hip").read_text()
+    m = re.search(r"constexpr int64_t kS1Chunk = (\d+);", src)
+    assert m, "kS1Chunk not found"
+    default = inspect.signature(stage_one_schedule).parameters["chunk"].default
+    assert int(m.group(1)) == default

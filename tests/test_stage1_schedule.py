@@ -270,3 +270,19 @@ def test_model_uses_the_library_chunk_length():
     assert m, "kS1Chunk not found"
     default = inspect.signature(stage_one_schedule).parameters["chunk"].default
     assert int(m.group(1)) == default
+
+
+def test_overlapped_schedule_has_no_race_over_a_grid_of_shapes():
+    """A grid of small shapes (n up to 41, panel widths 1..9, p 2..5, chunk
+    lengths 1, 3 and the library's), including panels with a single block and
+    the last panels' ragged blocks."""
+    count = 0
+    for n in (3, 4, 7, 12, 19, 28, 41):
+        for nb in (1, 2, 3, 5, 9):
+            if nb > n - 1:
+                continue
+            for p in (2, 3, 5):
+                for chunk in (1, 3, 8):
+                    assert races(stage_one_schedule(n, nb, p, overlap=True, chunk=chunk)) == [], (n, nb, p, chunk)
+                    count += 1
+    assert count > 250

@@ -486,7 +486,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               "(the reduction of one pencil is not sharded across devices).", file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ extern "C" {
 #define HT_ERR_HIP 1     /* a HIP runtime call failed */
 #define HT_ERR_NOMEM 2   /* device workspace allocation failed */
 #define HT_ERR_LAUNCH 3  /* a kernel launch failed */
-#define HT_ERR_NOTSUP 4  /* configuration not supported by this build */
+#define HT_ERR_NOTSUP 4  /* configuration not supported by the library */
 #define HT_ERR_TIMEOUT 5 /* a bounded device-side wait gave up (ht_stream_status) */
 #define HT_ERR_SCRATCH 6 /* workspace larger than the fixed scratch (ht_stage2_noalloc) */
 

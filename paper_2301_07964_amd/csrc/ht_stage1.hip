@@ -470,18 +470,19 @@ static size_t s1_workspace_bytes(int64_t n, int64_t nb, int64_t p, size_t elem)
 // ------------------------------------------------------------ overlap
 // The tasks of parallel stage one (Section 2.3): generating a panel's left
 // reflectors (block QRs) and right reflectors (the per-block factors with
-// their pass over B) stay on the caller's stream; applying them to Q (left)
+// their pass over B) stay on the caller's stream.  Applying them to Q (left)
 // and Z (right) depends on nothing else, and the left pass over A only has to
 // precede the right pass over A and the next block QR, so those three passes
-// run on a second stream `qz` beside the rest (during the QR of B, the pass
-// over A runs on the third stream, idle then).  In each block's pass over B only the rows that
-// the next factors read (from a lower bound L down the chain) stay on the
-// caller's stream; the rows above L go to a third stream `far`.  L is moved
-// down once every kS1Chunk blocks, and only then does the caller's stream wait
-// for the far rows already queued: adjacent blocks share columns, so rows
-// handed to `far` for block k+1 must be finished before the caller's stream
-// updates them for block k.  Every entry receives the same operations in the
-// same order as in the one-stream schedule, so the results are bitwise equal.
+// run on a second stream `qz` beside the rest.  In each block's pass over B
+// only the rows that the next factors read (from a lower bound L down the
+// chain) stay on the caller's stream; the rows above L go to a third stream
+// `far`, which during the QR of B (no factors yet) takes the passes over A
+// instead.  L is moved down once every kS1Chunk blocks, and only then does
+// the caller's stream wait for the far rows already queued: adjacent blocks
+// share columns, so rows handed to `far` for block k+1 must be finished before
+// the caller's stream updates them for block k.  Every entry receives the same
+// operations in the same order as in the one-stream schedule, so the results
+// are bitwise equal.
 constexpr int64_t kS1Chunk = 8;        // blocks per position of the bound L
 constexpr int64_t kS1OverlapMinN = 1024;
 

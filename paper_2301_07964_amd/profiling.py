@@ -17,6 +17,11 @@ not part of the reduction).
     python -m paper_2301_07964_amd.profiling mfma DIR
         FP64 matrix-core use per kernel from a pass with SQ_INSTS_VALU_MFMA_MOPS_F64,
         SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (markdown table)
+    python -m paper_2301_07964_amd.profiling streams DIR [FILTER [SPLIT]]
+        per queue and stream, from DIR/run_kernel_trace.csv: kernels, busy time
+        (sum of durations) and idle time (gaps between consecutive kernels) of
+        the kernels whose name contains FILTER; the span from the first to the
+        last of them, split at the first kernel whose name contains SPLIT
 
 The directories are rocprofv3 output directories written with
 ``--output-format csv -o run``.
@@ -174,6 +179,53 @@ def mfma_table(path: str, peak_tflops: float = 78.6, xcds: int = 8, simds: int =
     return "\n".join(lines)
 
 
+def streams(path: str, match: str = "", split: str | None = None):
+    """Per-stream occupancy of the kernels whose name contains `match`, from a
+    kernel-trace CSV: {"span_ms", "before_split_ms", "after_split_ms",
+    "streams": {(queue, stream): {"kernels", "busy_ms", "idle_ms", "names"}}}."""
+    f = os.path.join(path, "run_kernel_trace.csv") if os.path.isdir(path) else path
+    rows = []
+    with open(f, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if match in row["Kernel_Name"]:
+                rows.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]), row["Queue_Id"],
+                             row["Stream_Id"], short_name(row["Kernel_Name"])))
+    if not rows:
+        return {"span_ms": 0.0, "streams": {}}
+    rows.sort()
+    t0, t1 = rows[0][0], max(r[1] for r in rows)
+    out = {"span_ms": (t1 - t0) / 1e6, "streams": {}}
+    if split:
+        ts = next((r[0] for r in rows if split in r[4]), None)
+        if ts is not None:
+            out["before_split_ms"] = (ts - t0) / 1e6
+            out["after_split_ms"] = (t1 - ts) / 1e6
+    per = defaultdict(list)
+    for r in rows:
+        per[(r[2], r[3])].append(r)
+    for key, lst in sorted(per.items()):
+        busy = sum(e - b for b, e, *_ in lst)
+        idle = sum(max(0, b2 - e1) for (_, e1, *_), (b2, *_) in zip(lst, lst[1:]))
+        names = defaultdict(int)
+        for r in lst:
+            names[r[4]] += 1
+        out["streams"][key] = {"kernels": len(lst), "busy_ms": busy / 1e6, "idle_ms": idle / 1e6,
+                               "names": dict(names)}
+    return out
+
+
+def streams_table(path: str, match: str = "", split: str | None = None) -> str:
+    r = streams(path, match, split)
+    head = f"span {r['span_ms']:.1f} ms"
+    if "before_split_ms" in r:
+        head += f" ({r['before_split_ms']:.1f} ms before the first {split}, {r['after_split_ms']:.1f} ms from it)"
+    lines = [head, "", "| queue / stream | kernels | busy ms | idle ms | kernels by name |", "|---|---|---|---|---|"]
+    for (q, st), a in r["streams"].items():
+        names = ", ".join(f"`{k}` {v}" for k, v in sorted(a["names"].items()))
+        lines.append(f"| {q} / {st} | {a['kernels']} | {a['busy_ms']:.1f} | {a['idle_ms']:.1f} | {names} |")
+    return "\n".join(lines)
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(stats_table(argv[1]))
@@ -186,6 +238,8 @@ def main(argv):
                                 argv[6] if len(argv) > 6 else None), indent=1))
     elif len(argv) >= 2 and argv[0] == "mfma":
         print(mfma_table(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "streams":
+        print(streams_table(argv[1], argv[2] if len(argv) > 2 else "", argv[3] if len(argv) > 3 else None))
     else:
         print(__doc__)
         return 2

@@ -106,3 +106,31 @@ def test_bench_uses_a_traffic_record_only_for_unchanged_sources(tmp_path, monkey
     assert bench.measured_traffic("k_absent") is None
     src.write_text("kernel source, changed\n")
     assert bench.measured_traffic("k_generate<double>") is None
+
+
+def test_streams_busy_idle_and_split(tmp_path):
+    """Per-stream busy time (sum of durations), idle time (gaps between
+    consecutive kernels of the stream) and the span split at a kernel."""
+    from paper_2301_07964_amd import profiling as P
+    f = tmp_path / "run_kernel_trace.csv"
+    rows = [  # (queue, stream, name, start, end) in ns
+        (1, 0, "void ht::k_s1_block_qr<double>(double*)", 0, 1_000_000),
+        (1, 0, "void ht::k_s1_right_factor<double>(double*)", 1_500_000, 2_000_000),
+        (1, 0, "void ht::k_s1_right_factor<double>(double*)", 2_000_000, 2_600_000),
+        (2, 1, "void ht::k_s1_right_chain<double>(double*)", 1_200_000, 1_400_000),
+        (2, 1, "void ht::k_s1_right_chain<double>(double*)", 2_400_000, 3_000_000),
+        (1, 0, "void at::native::fill<double>(double*)", 5_000_000, 9_000_000),
+    ]
+    with open(f, "w") as fh:
+        fh.write('"Kind","Queue_Id","Stream_Id","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        for q, st, name, b, e in rows:
+            fh.write(f'"KERNEL_DISPATCH",{q},{st},"{name}",{b},{e}\n')
+    r = P.streams(str(tmp_path), "k_s1", "right_factor")
+    assert r["span_ms"] == pytest.approx(3.0)
+    assert r["before_split_ms"] == pytest.approx(1.5) and r["after_split_ms"] == pytest.approx(1.5)
+    main, side = r["streams"][("1", "0")], r["streams"][("2", "1")]
+    assert main["kernels"] == 3 and main["busy_ms"] == pytest.approx(2.1) and main["idle_ms"] == pytest.approx(0.5)
+    assert side["kernels"] == 2 and side["busy_ms"] == pytest.approx(0.8) and side["idle_ms"] == pytest.approx(1.0)
+    assert main["names"] == {"ht::k_s1_block_qr<double>": 1, "ht::k_s1_right_factor<double>": 2}
+    table = P.streams_table(str(tmp_path), "k_s1", "right_factor")
+    assert "| 1 / 0 | 3 | 2.1 | 0.5 |" in table and "span 3.0 ms" in table
